@@ -220,6 +220,17 @@ def cs_estimate(table) -> tuple[int, np.ndarray]:
     return int(med.value), rows_out
 
 
+def cs_estimate_status(table) -> tuple[int, int, np.ndarray]:
+    """(status, median, per-row X_j) without raising; an X_j that does not fit
+    in int64 reads INT64_MAX and the status is EOVERFLOW."""
+    table = np.ascontiguousarray(np.asarray(table, dtype=np.int64))
+    rows, m = table.shape
+    rows_out = np.zeros(rows, dtype=np.int64)
+    med = ctypes.c_int64(0)
+    st = _load().orc_cs_estimate(_ptr(table), rows, m, _ptr(rows_out), ctypes.byref(med))
+    return int(st), int(med.value), rows_out
+
+
 def exact_f2(keys, weights) -> int:
     keys = _u64(keys).reshape(-1)
     weights = _i64(weights).reshape(-1)

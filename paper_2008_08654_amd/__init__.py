@@ -1,0 +1,236 @@
+"""Python binding of libmcs.so (include/mcs.h) -- argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; this module converts
+torch tensors to device pointers and HIP streams to handles, calls the C ABI
+through ctypes and turns non-zero statuses into exceptions.  There is no
+fallback: if libmcs.so is missing, importing the binding functions raises.
+
+Build the library first with ``python -m paper_2008_08654_amd.build`` (or
+``__graft_entry__.build()``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcs.so")
+
+# enums mirrored from include/mcs.h
+CS_OK, CS_EINVAL, CS_ENOMEM, CS_EDOMAIN, CS_EOVERFLOW, CS_EDEVICE, CS_EBUSY = 0, -1, -2, -3, -4, -5, -6
+CS_P61, CS_P89, CS_P64_59 = 1, 2, 3
+CS_TWO_FOR_ONE, CS_TWO_FOR_ONE_MSB, CS_TWO_POLY = 0, 1, 2
+CS_U32, CS_U64, CS_I32, CS_I64 = 0, 1, 2, 3
+CS_PATH_AUTO, CS_PATH_LDS, CS_PATH_GLOBAL, CS_PATH_BINNED = 0, 1, 2, 3
+
+_STATUS_NAMES = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ENOMEM", -3: "CS_EDOMAIN", -4: "CS_EOVERFLOW",
+                 -5: "CS_EDEVICE", -6: "CS_EBUSY"}
+
+_lib = None
+
+
+class MCSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libmcs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2008_08654_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        sig = {
+            "cs_create": [u32, u64, i32, u64, P],
+            "cs_create_ex": [u32, u64, i32, u64, i32, u32, P],
+            "cs_create_with_coeffs": [u32, u64, i32, i32, u32, P, P],
+            "cs_update": [P, P, i32, P, i32, u64, P],
+            "cs_estimate_f2": [P, P, P, P],
+            "cs_query": [P, P, i32, u64, P, P],
+            "cs_read_counters": [P, P, P],
+            "cs_table_device": [P, P],
+            "cs_read_coeffs": [P, P],
+            "cs_info": [P, P, P, P, P, P],
+            "cs_reset": [P, P],
+            "cs_merge": [P, P, P],
+            "cs_sync": [P, P],
+            "cs_set_update_path": [P, i32],
+            "mersenne_divmod": [i32, P, u64, P, P, P],
+            "mersenne_div": [i32, P, u64, P, P],
+            "mersenne_mod": [i32, P, u64, P, P],
+            "mersenne_divmod_naive": [i32, P, u64, P, P, P],
+            "mersenne_status": [P],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = i32
+        L.cs_destroy.argtypes = [P]
+        L.cs_destroy.restype = None
+        L.cs_last_error.restype = ctypes.c_char_p
+        L.cs_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != CS_OK:
+        raise MCSError(st, lib().cs_last_error().decode())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    """HIP stream handle: None -> torch's current stream on the current device."""
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t) -> ctypes.c_void_p:
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _key_dtype(t) -> int:
+    import torch
+    if t.dtype in (torch.int32, torch.uint32):
+        return CS_U32
+    if t.dtype in (torch.int64, torch.uint64):
+        return CS_U64
+    raise ValueError(f"unsupported key dtype {t.dtype}")
+
+
+def _weight_dtype(t) -> int:
+    import torch
+    if t.dtype == torch.int32:
+        return CS_I32
+    if t.dtype == torch.int64:
+        return CS_I64
+    raise ValueError(f"unsupported weight dtype {t.dtype}")
+
+
+def npoly(mode: int) -> int:
+    return 2 if mode == CS_TWO_POLY else 1
+
+
+class Sketch:
+    """Owning handle of a cs_sketch (rows x buckets int64 counters on the current device)."""
+
+    def __init__(self, rows: int, buckets: int, prime: int = CS_P61, seed: int = 0, mode: int = CS_TWO_FOR_ONE,
+                 k: int = 4, coeffs: np.ndarray | None = None):
+        self._h = ctypes.c_void_p()
+        if coeffs is None:
+            _check(lib().cs_create_ex(rows, buckets, prime, seed & 0xFFFFFFFFFFFFFFFF, mode, k, ctypes.byref(self._h)))
+        else:
+            c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.uint64))
+            _check(lib().cs_create_with_coeffs(rows, buckets, prime, mode, k, c.ctypes.data_as(ctypes.c_void_p),
+                                               ctypes.byref(self._h)))
+        self.rows, self.buckets, self.prime, self.mode, self.k = rows, buckets, prime, mode, k
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().cs_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # Algorithm 2, Process over a batch
+    def update(self, keys, weights, stream=None, n: int | None = None):
+        n = keys.numel() if n is None else n
+        if weights.numel() < n or keys.numel() < n:
+            raise ValueError("keys/weights shorter than n")
+        _check(lib().cs_update(self._h, _dev_ptr(keys), _key_dtype(keys), _dev_ptr(weights), _weight_dtype(weights),
+                               n, _stream(stream)))
+
+    # Algorithm 2, Output + median over rows
+    def estimate_f2(self, stream=None) -> tuple[int, np.ndarray]:
+        f2 = ctypes.c_int64()
+        rows = np.zeros(self.rows, dtype=np.int64)
+        _check(lib().cs_estimate_f2(self._h, ctypes.byref(f2), rows.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return int(f2.value), rows
+
+    def estimate_f2_status(self, stream=None) -> tuple[int, int, np.ndarray]:
+        """Like estimate_f2 but returns the status instead of raising."""
+        f2 = ctypes.c_int64()
+        rows = np.zeros(self.rows, dtype=np.int64)
+        st = lib().cs_estimate_f2(self._h, ctypes.byref(f2), rows.ctypes.data_as(ctypes.c_void_p), _stream(stream))
+        return st, int(f2.value), rows
+
+    def query(self, keys, out, stream=None):
+        _check(lib().cs_query(self._h, _dev_ptr(keys), _key_dtype(keys), keys.numel(), _dev_ptr(out), _stream(stream)))
+
+    def counters(self, stream=None) -> np.ndarray:
+        out = np.zeros((self.rows, self.buckets), dtype=np.int64)
+        _check(lib().cs_read_counters(self._h, out.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return out
+
+    def table_ptr(self) -> int:
+        p = ctypes.c_void_p()
+        _check(lib().cs_table_device(self._h, ctypes.byref(p)))
+        return p.value
+
+    def coeffs(self) -> np.ndarray:
+        count = self.rows * npoly(self.mode) * self.k
+        out = np.zeros(count * (2 if self.prime == CS_P89 else 1), dtype=np.uint64)
+        _check(lib().cs_read_coeffs(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out.reshape(count, 2) if self.prime == CS_P89 else out
+
+    def set_update_path(self, path: int):
+        _check(lib().cs_set_update_path(self._h, path))
+
+    def reset(self, stream=None):
+        _check(lib().cs_reset(self._h, _stream(stream)))
+
+    def merge(self, other: "Sketch", stream=None):
+        _check(lib().cs_merge(self._h, other._h, _stream(stream)))
+
+    def sync(self, stream=None):
+        _check(lib().cs_sync(self._h, _stream(stream)))
+
+
+def mersenne_divmod(prime: int, x, quot=None, rem=None, stream=None, naive: bool = False):
+    """Quotient/remainder of x (uint64 limbs as int64 tensor, shape (n, 2) or (n, 3)) by the prime."""
+    n = x.shape[0]
+    fn = lib().mersenne_divmod_naive if naive else lib().mersenne_divmod
+    _check(fn(prime, _dev_ptr(x), n, _dev_ptr(quot) if quot is not None else None,
+              _dev_ptr(rem) if rem is not None else None, _stream(stream)))
+
+
+def mersenne_div(prime: int, x, quot, stream=None):
+    _check(lib().mersenne_div(prime, _dev_ptr(x), x.shape[0], _dev_ptr(quot), _stream(stream)))
+
+
+def mersenne_mod(prime: int, x, rem, stream=None):
+    _check(lib().mersenne_mod(prime, _dev_ptr(x), x.shape[0], _dev_ptr(rem), _stream(stream)))
+
+
+def mersenne_status(stream=None):
+    _check(lib().mersenne_status(_stream(stream)))
+
+
+def version() -> str:
+    return lib().cs_version().decode()

@@ -1,0 +1,154 @@
+// sketch_kernels.hpp -- launch interface between the host library and the
+// Count Sketch / quotient-remainder kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "field.hpp"
+
+namespace mcs {
+
+constexpr int kPrime61 = 1;
+constexpr int kPrime89 = 2;
+constexpr int kPrime64c = 3;
+constexpr int kTwoForOne = 0;
+constexpr int kTwoForOneMsb = 1;
+constexpr int kTwoPoly = 2;
+
+constexpr int kBlock = 256;          // 4 wave64s
+constexpr int kKeysPerThread = 4;    // keys held in registers per thread per tile
+constexpr uint32_t kMaxRows = 64;    // rows per sketch
+constexpr uint32_t kMaxQueryRows = 64;
+constexpr uint32_t kMaxLog2m = 30;
+
+// sticky device flags
+constexpr uint32_t kFlagDomain = 1u;
+constexpr uint32_t kFlagOverflow = 2u;
+
+constexpr int kVariantLds = 0;
+constexpr int kVariantGlobal = 1;
+constexpr int kVariantBinned = 2;
+
+// two-pass (binned) update
+constexpr int kBinKpt = 8;                          // keys per thread in a pass-1 tile
+constexpr uint32_t kBinTile = kBlock * kBinKpt;     // keys per tile
+constexpr uint32_t kRangeLog2 = 14;                 // counters per partition (int64 LDS table in pass 2)
+constexpr uint32_t kRecWeightBits = 18;             // signed weight field of a record
+constexpr int kAccBlock = 1024;                     // pass-2 block (16 wave64s)
+constexpr uint32_t kMaxLog2g = 8;                   // at most 256 ranges per row
+
+struct UpdatePlan {
+  int variant;
+  uint32_t blocks;
+  uint32_t lds_bytes;
+  // binned variant
+  uint32_t log2g;       // log2 of bucket ranges per row
+  uint32_t tiles;       // tiles in this launch
+  uint32_t acc_slices;  // pass-2 blocks per partition
+  uint32_t* recs;       // [tiles][rows][kBinTile]
+  uint32_t* desc;       // [tiles][rows][G + 1]
+};
+
+template <typename KeyT, typename WT>
+struct UpdateArgs {
+  const KeyT* keys;
+  const WT* weights;
+  uint64_t n;
+  uint64_t keys_per_block;
+  const uint4* coeffs;
+  uint32_t rows;
+  uint32_t log2m;
+  unsigned long long* table;
+  uint32_t* flags;
+};
+
+struct UpdateArgsAny {
+  int prime, mode, k;
+  int key_bytes, weight_bytes;
+  const void* keys;
+  const void* weights;
+  uint64_t n;
+  uint64_t keys_per_block;
+  const uint4* coeffs;
+  uint32_t rows;
+  uint32_t log2m;
+  unsigned long long* table;
+  uint32_t* flags;
+  template <typename KeyT, typename WT>
+  UpdateArgs<KeyT, WT> as() const {
+    return UpdateArgs<KeyT, WT>{(const KeyT*)keys, (const WT*)weights, n, keys_per_block, coeffs, rows, log2m,
+                                table, flags};
+  }
+};
+
+template <typename KeyT, typename WT>
+struct BinArgs {
+  const KeyT* keys;
+  const WT* weights;
+  uint64_t n;
+  const uint4* coeffs;
+  uint32_t rows;
+  uint32_t log2m;
+  uint32_t log2g;
+  uint32_t tiles;
+  uint32_t* recs;
+  uint32_t* desc;
+  unsigned long long* table;
+  uint32_t* flags;
+};
+
+struct AccArgs {
+  const uint32_t* recs;
+  const uint32_t* desc;
+  uint32_t tiles;
+  uint32_t rows;
+  uint32_t log2m;
+  uint32_t log2g;
+  unsigned long long* table;
+};
+
+template <typename KeyT>
+struct QueryArgs {
+  const KeyT* keys;
+  uint64_t n;
+  const uint4* coeffs;
+  uint32_t rows;
+  uint32_t log2m;
+  const int64_t* table;
+  int64_t* out;
+  uint32_t* flags;
+};
+
+struct QueryArgsAny {
+  int prime, mode, k, key_bytes;
+  const void* keys;
+  uint64_t n;
+  const uint4* coeffs;
+  uint32_t rows;
+  uint32_t log2m;
+  const int64_t* table;
+  int64_t* out;
+  uint32_t* flags;
+  template <typename KeyT>
+  QueryArgs<KeyT> as() const {
+    return QueryArgs<KeyT>{(const KeyT*)keys, n, coeffs, rows, log2m, table, out, flags};
+  }
+};
+
+struct EstPartial {
+  unsigned long long lo, hi;
+  uint32_t big, pad;
+};
+
+hipError_t launch_update(const UpdatePlan& plan, const UpdateArgsAny& a, hipStream_t st);
+hipError_t launch_query(const QueryArgsAny& a, hipStream_t st);
+hipError_t launch_estimate(const int64_t* table, uint32_t rows, uint32_t log2m, uint32_t slices, EstPartial* part,
+                           int64_t* out, uint32_t* flags, hipStream_t st);
+hipError_t launch_add_tables(unsigned long long* dst, const unsigned long long* src, uint64_t n, hipStream_t st);
+hipError_t launch_fill_zero(unsigned long long* dst, uint64_t n, hipStream_t st);
+
+// quotient / remainder
+hipError_t launch_divmod(int prime, bool naive, const uint64_t* x, uint64_t n, uint64_t* quot, uint64_t* rem,
+                         uint32_t* flags, hipStream_t st);
+
+}  // namespace mcs

@@ -1,0 +1,314 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, bit-exact.
+
+Inputs come from ``workloads`` (seeded, synthetic); expected values from
+``oracle`` only.  Sizes span several 1024-key tiles plus a ragged tail.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+try:
+    import paper_2008_08654_amd as M
+except Exception:  # pragma: no cover
+    M = None
+
+DEV = "cuda:0"
+
+PRIMES = {M.CS_P61 if M else 1: O.PRIME_P61, M.CS_P89 if M else 2: O.PRIME_P89}
+
+
+def _u64(t: torch.Tensor) -> np.ndarray:
+    """Host uint64 values of a key tensor (int32 tensors hold uint32 bit patterns)."""
+    a = t.detach().cpu().numpy()
+    if a.dtype == np.int32:
+        return a.view(np.uint32).astype(np.uint64)
+    return a.view(np.uint64)
+
+
+def _oracle_table(sk, keys, weights):
+    coeffs = O.coeffs_from_seed(PRIMES[sk.prime], sk.rows, sk.mode, seed=sk._seed, k=sk.k) \
+        if getattr(sk, "_seed", None) is not None else sk._coeffs
+    return O.cs_update(PRIMES[sk.prime], sk.mode, sk.rows, sk.buckets, coeffs, _u64(keys),
+                       weights.detach().cpu().numpy().astype(np.int64), k=sk.k)
+
+
+def _make(rows, m, prime, seed, mode=0, k=4):
+    sk = M.Sketch(rows, m, prime=prime, seed=seed, mode=mode, k=k)
+    sk._seed = seed
+    return sk
+
+
+def _check_sketch(sk, keys, weights, table=None):
+    torch.cuda.synchronize()
+    got = sk.counters()
+    want = _oracle_table(sk, keys, weights) if table is None else table
+    assert np.array_equal(got, want), f"{int((got != want).sum())} counters differ"
+    st, f2, rows = sk.estimate_f2_status()
+    wst, wmed, wrows = O.cs_estimate_status(want)
+    assert st == {O.OK: M.CS_OK, O.EOVERFLOW: M.CS_EOVERFLOW}[wst]
+    assert list(rows) == list(wrows) and f2 == wmed
+    return want
+
+
+def test_coefficients_match_oracle():
+    for prime in (M.CS_P61, M.CS_P89):
+        for mode in (0, 1, 2):
+            sk = M.Sketch(7, 64, prime=prime, seed=123456789, mode=mode, k=4)
+            want = O.coeffs_from_seed(PRIMES[prime], 7, mode, seed=123456789)
+            assert np.array_equal(sk.coeffs(), want)
+
+
+def test_single_stream_u32_workload_bit_exact():
+    """n = 2^16 uint32 keys uniform, weights int64 = 1, p = 2^61-1, t = 5, m = 2^10."""
+    keys, w = W.stream_small_u32(1 << 16)
+    keys = keys.to(torch.int32).to(DEV)  # uint32 bit patterns
+    w = w.to(DEV)
+    sk = _make(5, 1 << 10, M.CS_P61, seed=1001)
+    sk.update(keys, w)
+    table = _check_sketch(sk, keys, w)
+    exact = O.exact_f2(_u64(keys), w.cpu().numpy())
+    f2, _ = sk.estimate_f2()
+    assert abs(f2 - exact) / exact < 0.25
+    assert int(np.abs(table).sum()) > 0
+
+
+@pytest.mark.parametrize("prime", [1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("kt,wt", [("u32", "i32"), ("u32", "i64"), ("u64", "i32"), ("u64", "i64")])
+def test_modes_primes_dtypes(prime, mode, kt, wt):
+    n = 5 * 1024 + 77
+    g = torch.Generator().manual_seed(prime * 100 + mode * 10 + len(kt + wt))
+    if kt == "u32":
+        keys = W.uniform_u32(7 + mode, n).to(torch.int32)
+    else:
+        keys = W.uniform_u64(7 + mode, n)
+        if prime == M.CS_P61:
+            keys = keys & ((1 << 60) - 1)
+            keys[: 3 * 1024] &= 0xFFFFFFFF  # first waves take the one-limb path
+    if wt == "i32":
+        w = torch.randint(-(1 << 31), (1 << 31) - 1, (n,), generator=g, dtype=torch.int64).to(torch.int32)
+    else:
+        w = torch.randint(-(1 << 62), 1 << 62, (n,), generator=g, dtype=torch.int64)
+    keys, w = keys.to(DEV), w.to(DEV)
+    sk = _make(3, 256, prime, seed=40 + prime, mode=mode)
+    sk.update(keys, w)
+    _check_sketch(sk, keys, w)
+
+
+def test_large_table_zipf_two_for_one_and_two_poly():
+    """t = 9, m = 2^16 (4.5 MiB table) on 2^17 Zipf(1.1) keys with int32 weights in [-100, 100]."""
+    keys, w = W.stream_zipf_u64(1 << 17)
+    keys, w = keys.to(DEV), w.to(DEV)
+    for mode in (M.CS_TWO_FOR_ONE, M.CS_TWO_POLY):
+        sk = _make(9, 1 << 16, M.CS_P61, seed=1002, mode=mode)
+        sk.update(keys, w)
+        _check_sketch(sk, keys, w)
+
+
+@pytest.mark.parametrize("path", [2, 3])
+@pytest.mark.parametrize("rows,log2m,prime,mode", [
+    (9, 16, 1, 0), (9, 16, 1, 2), (5, 20, 2, 0), (64, 10, 1, 1), (3, 15, 2, 2), (2, 22, 1, 0)])
+def test_forced_paths_match_oracle(path, rows, log2m, prime, mode):
+    """The global-atomic and the two-pass (binned) update give the oracle's counters,
+    including ragged tiles, bucket ranges smaller than one partition, and weights too
+    large for a record (they take the direct atomic)."""
+    n = 3 * 2048 + 555
+    keys = W.zipf(31 + log2m, n, 1.1, 1 << 32)
+    w = W.bounded_int(31 + log2m, n, -100, 100)
+    w[::97] = torch.randint(-(1 << 62), 1 << 62, w[::97].shape, generator=torch.Generator().manual_seed(1))
+    w[1::89] = 1 << 17
+    w[2::89] = -(1 << 17)
+    w[3::89] = (1 << 17) - 1
+    w[4::89] = -(1 << 17) + 1
+    keys, w = keys.to(DEV), w.to(DEV)
+    sk = _make(rows, 1 << log2m, prime, seed=500 + log2m, mode=mode)
+    sk.set_update_path(path)
+    sk.update(keys, w)
+    sk.update(keys[: n // 3].contiguous(), w[: n // 3].contiguous())
+    want = _oracle_table(sk, keys, w)
+    _oracle_add = O.cs_update(PRIMES[prime], mode, rows, 1 << log2m,
+                              O.coeffs_from_seed(PRIMES[prime], rows, mode, seed=500 + log2m),
+                              _u64(keys[: n // 3]), w[: n // 3].cpu().numpy(), table=want)
+    _check_sketch(sk, keys, w, table=want)
+
+
+def test_lds_path_forced_on_small_table():
+    keys, w = W.stream_zipf_u64(10000, seed=3)
+    keys, w = keys.to(DEV), w.to(DEV)
+    sk = _make(4, 1 << 11, M.CS_P61, seed=9)
+    sk.set_update_path(M.CS_PATH_LDS)
+    sk.update(keys, w)
+    _check_sketch(sk, keys, w)
+
+
+def test_p89_large_table_uniform_u64():
+    """p = 2^89-1, t = 5, m = 2^20 (40 MiB table), uniform uint64 keys, int64 weights = 1."""
+    keys, w = W.stream_uniform_u64(1 << 15)
+    keys, w = keys.to(DEV), w.to(DEV)
+    sk = _make(5, 1 << 20, M.CS_P89, seed=1003)
+    sk.update(keys, w)
+    _check_sketch(sk, keys, w)
+
+
+@pytest.mark.parametrize("k", [2, 8])
+@pytest.mark.parametrize("prime", [1, 2])
+def test_polynomial_degrees(k, prime):
+    keys = W.uniform_u64(5, 3000)
+    if prime == M.CS_P61:
+        keys = keys & ((1 << 60) - 1)
+    w = W.bounded_int(5, 3000, -50, 50)
+    keys, w = keys.to(DEV), w.to(DEV)
+    sk = _make(4, 512, prime, seed=77, k=k)
+    sk.update(keys, w)
+    _check_sketch(sk, keys, w)
+
+
+def test_empty_stream_and_edge_keys():
+    sk = _make(5, 1024, M.CS_P61, seed=3)
+    empty = torch.empty(0, dtype=torch.int64, device=DEV)
+    sk.update(empty, empty)
+    f2, rows = sk.estimate_f2()
+    assert f2 == 0 and not rows.any() and not sk.counters().any()
+    edge = torch.tensor([0, 1, 2, (1 << 32) - 1, 1 << 32, (1 << 59), (1 << 60) - 1, (1 << 60) - 2], device=DEV)
+    w = torch.tensor([1, -1, 5, 7, -9, 11, 13, -(1 << 40)], device=DEV)
+    sk.update(edge, w)
+    _check_sketch(sk, edge, w)
+    sk89 = _make(3, 1 << 12, M.CS_P89, seed=4, mode=M.CS_TWO_FOR_ONE_MSB)
+    e89 = torch.tensor([0, 1, -1, -2, -(1 << 63), (1 << 63) - 1, 1 << 32], device=DEV)  # -1 = 2^64-1
+    w89 = torch.ones(7, dtype=torch.int64, device=DEV)
+    sk89.update(e89, w89)
+    _check_sketch(sk89, e89, w89)
+
+
+def test_domain_error_is_sticky_and_reset_clears_it():
+    sk = _make(2, 64, M.CS_P61, seed=5)
+    bad = torch.tensor([1, 1 << 60, 3], device=DEV)
+    sk.update(bad, torch.ones(3, dtype=torch.int64, device=DEV))
+    st, _, _ = sk.estimate_f2_status()
+    assert st == M.CS_EDOMAIN
+    with pytest.raises(M.MCSError):
+        sk.sync()
+    sk.reset()
+    sk.sync()
+    assert not sk.counters().any()
+
+
+def test_estimate_overflow():
+    sk = _make(3, 64, M.CS_P61, seed=6)
+    keys = torch.tensor([5], device=DEV)
+    sk.update(keys, torch.tensor([1 << 32], device=DEV))
+    st, f2, rows = sk.estimate_f2_status()
+    assert st == M.CS_EOVERFLOW and f2 == np.iinfo(np.int64).max
+    with pytest.raises(O.OracleError):
+        O.cs_estimate(sk.counters())  # the counters stay readable
+    # overflow concerns that estimate only: after cancelling the key it fits again
+    sk.update(keys, torch.tensor([-(1 << 32) + 3], device=DEV))
+    f2, rows = sk.estimate_f2()
+    assert f2 == 9 and list(rows) == [9, 9, 9]
+
+
+def test_point_query_matches_oracle():
+    keys, w = W.stream_zipf_u64(20000, seed=99)
+    keys, w = keys.to(DEV), w.to(DEV)
+    for prime in (M.CS_P61, M.CS_P89):
+        sk = _make(5, 1 << 10, prime, seed=8)
+        sk.update(keys, w)
+        table = sk.counters()
+        q = keys[:500].contiguous()
+        out = torch.empty(500, dtype=torch.int64, device=DEV)
+        sk.query(q, out)
+        torch.cuda.synchronize()
+        coeffs = O.coeffs_from_seed(PRIMES[prime], 5, 0, seed=8)
+        want = []
+        for x in _u64(q):
+            vals = []
+            for r in range(5):
+                b, s = O.bucket_sign(PRIMES[prime], 0, 1 << 10, coeffs, r, int(x))
+                vals.append(s * int(table[r, b]))
+            want.append(sorted(vals)[2])
+        assert out.cpu().tolist() == want
+
+
+def test_linearity_merge_and_split_updates():
+    keys, w = W.stream_zipf_u64(50000, seed=5)
+    keys, w = keys.to(DEV), w.to(DEV)
+    for m in (1 << 8, 1 << 16):
+        a = _make(5, m, M.CS_P61, seed=10)
+        b = _make(5, m, M.CS_P61, seed=10)
+        whole = _make(5, m, M.CS_P61, seed=10)
+        a.update(keys[:20000].contiguous(), w[:20000].contiguous())
+        b.update(keys[20000:].contiguous(), w[20000:].contiguous())
+        whole.update(keys, w)
+        a.merge(b)
+        assert np.array_equal(a.counters(), whole.counters())
+        whole.update(keys, -w)
+        assert not whole.counters().any()
+
+
+# ---------------------------------------------------------------------------
+# quotient and remainder
+# ---------------------------------------------------------------------------
+def _divmod_inputs(prime, n, seed):
+    p = {M.CS_P61: O.P61, M.CS_P89: O.P89, M.CS_P64_59: O.P64_59}[prime]
+    nl = 3 if prime == M.CS_P89 else 2
+    x = W.below_limbs(p * p, nl, seed, n)
+    extra = [0, 1, p - 1, p, p + 1, 2 * p - 1, 2 * p, p * p - 1, 12345 * p, 12345 * p - 1, (2 ** 64 - 1),
+             2 ** 64, 2 ** 64 + 1]
+    if prime == M.CS_P61:
+        extra += [2 ** 122 - 1, 2 ** 122 - 2, p * p, (2 ** 61 + 1) * p - 1]  # Mersenne domain beyond p^2
+    elif prime == M.CS_P89:
+        extra += [2 ** 178 - 1, 2 ** 178 - 2, p * p, 2 ** 128 - 1, 2 ** 128, 2 ** 128 + 1]
+    else:
+        extra += [p * 2 ** 64 - 1, 2 ** 127, (2 ** 64 - 60) * p + (p - 1)]
+    ex = torch.tensor([[((v >> (64 * j)) & (2 ** 64 - 1)) - (2 ** 64 if (v >> (64 * j + 63)) & 1 else 0)
+                        for j in range(nl)] for v in extra], dtype=torch.int64)
+    return torch.cat([x, ex]).contiguous()
+
+
+@pytest.mark.parametrize("prime", [1, 2, 3])
+@pytest.mark.parametrize("naive", [False, True])
+def test_divmod_matches_oracle(prime, naive):
+    x = _divmod_inputs(prime, 100003, seed=prime)
+    n = x.shape[0]
+    qw = 2 if prime == M.CS_P89 else 1
+    xd = x.to(DEV)
+    q = torch.empty((n, qw), dtype=torch.int64, device=DEV)
+    r = torch.empty((n, qw), dtype=torch.int64, device=DEV)
+    M.mersenne_divmod(prime, xd, q, r, naive=naive)
+    M.mersenne_status()
+    oprime = {1: O.PRIME_P61, 2: O.PRIME_P89, 3: O.PRIME_P64_59}[prime]
+    wq, wr = O.divmod_batch(oprime, x.numpy().view(np.uint64))
+    assert np.array_equal(q.cpu().numpy().view(np.uint64).reshape(wq.shape), wq)
+    assert np.array_equal(r.cpu().numpy().view(np.uint64).reshape(wr.shape), wr)
+
+
+@pytest.mark.parametrize("prime", [1, 2, 3])
+def test_div_and_mod_alone(prime):
+    x = _divmod_inputs(prime, 4097, seed=10 + prime)
+    n = x.shape[0]
+    qw = 2 if prime == M.CS_P89 else 1
+    xd = x.to(DEV)
+    q = torch.empty((n, qw), dtype=torch.int64, device=DEV)
+    r = torch.empty((n, qw), dtype=torch.int64, device=DEV)
+    M.mersenne_div(prime, xd, q)
+    M.mersenne_mod(prime, xd, r)
+    M.mersenne_status()
+    oprime = {1: O.PRIME_P61, 2: O.PRIME_P89, 3: O.PRIME_P64_59}[prime]
+    wq, wr = O.divmod_batch(oprime, x.numpy().view(np.uint64))
+    assert np.array_equal(q.cpu().numpy().view(np.uint64).reshape(wq.shape), wq)
+    assert np.array_equal(r.cpu().numpy().view(np.uint64).reshape(wr.shape), wr)
+
+
+def test_divmod_domain_flag():
+    x = torch.tensor([[5, 0], [0, 1 << 58]], dtype=torch.int64, device=DEV)  # second value = 2^122
+    q = torch.empty(2, dtype=torch.int64, device=DEV)
+    M.mersenne_divmod(M.CS_P61, x, q, None)
+    with pytest.raises(M.MCSError) as e:
+        M.mersenne_status()
+    assert e.value.status == M.CS_EDOMAIN
+    M.mersenne_status()  # cleared
