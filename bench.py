@@ -82,10 +82,15 @@ def cpu_baseline_sketch(keys_dev, w_dev, wl, budget_s=15.0):
         a = t[:n].cpu().numpy()
         return a.view(np.uint32).astype(np.uint64) if a.dtype == np.int32 else a.view(np.uint64)
 
-    n_probe = 1 << 14
-    t0 = time.perf_counter()
-    O.cs_update(prime, mode, rows, m, coeffs, host(keys_dev, n_probe), w_dev[:n_probe].cpu().numpy().astype(np.int64))
-    dt = time.perf_counter() - t0
+    n_probe, dt = 1 << 14, 0.0
+    while True:  # grow the probe until it takes a second, then scale to the budget
+        kp, wp = host(keys_dev, n_probe), w_dev[:n_probe].cpu().numpy().astype(np.int64)
+        t0 = time.perf_counter()
+        O.cs_update(prime, mode, rows, m, coeffs, kp, wp)
+        dt = time.perf_counter() - t0
+        if dt > 1.0 or n_probe >= keys_dev.numel():
+            break
+        n_probe = min(keys_dev.numel(), n_probe * 4)
     n = int(min(keys_dev.numel(), max(n_probe, n_probe * budget_s / max(dt, 1e-6))))
     k = host(keys_dev, n)
     w = w_dev[:n].cpu().numpy().astype(np.int64)

@@ -121,10 +121,13 @@ cs_status cs_query(cs_sketch* s, const void* keys, cs_dtype key_type, uint64_t n
                    hipStream_t stream);
 
 /* Update paths.  AUTO picks LDS when the whole table (rows*buckets*8 bytes)
- * fits in 64 KiB, else BINNED (two passes through a library-owned workspace,
- * buckets <= 2^22), else GLOBAL (one device-scope atomic per key and row).
- * All paths give identical counters; forcing one is for testing and tuning. */
-enum { CS_PATH_AUTO = 0, CS_PATH_LDS = 1, CS_PATH_GLOBAL = 2, CS_PATH_BINNED = 3 };
+ * fits in 64 KiB, else BINNED (two passes through a library-owned workspace),
+ * else GLOBAL (one device-scope atomic per key and row).  BINNED first
+ * combines repeated keys within each tile of 2048 keys (the sketch is linear,
+ * so C[i(x)] += s(x) * (sum of their weights) is the same update);
+ * BINNED_NOCOMBINE skips that step.  All paths give identical counters;
+ * forcing one is for testing and tuning. */
+enum { CS_PATH_AUTO = 0, CS_PATH_LDS = 1, CS_PATH_GLOBAL = 2, CS_PATH_BINNED = 3, CS_PATH_BINNED_NOCOMBINE = 4 };
 cs_status cs_set_update_path(cs_sketch* s, int path);
 
 /* Copies the rows*buckets counters (row-major) to host memory; synchronises. */

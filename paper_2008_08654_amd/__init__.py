@@ -23,7 +23,7 @@ CS_OK, CS_EINVAL, CS_ENOMEM, CS_EDOMAIN, CS_EOVERFLOW, CS_EDEVICE, CS_EBUSY = 0,
 CS_P61, CS_P89, CS_P64_59 = 1, 2, 3
 CS_TWO_FOR_ONE, CS_TWO_FOR_ONE_MSB, CS_TWO_POLY = 0, 1, 2
 CS_U32, CS_U64, CS_I32, CS_I64 = 0, 1, 2, 3
-CS_PATH_AUTO, CS_PATH_LDS, CS_PATH_GLOBAL, CS_PATH_BINNED = 0, 1, 2, 3
+CS_PATH_AUTO, CS_PATH_LDS, CS_PATH_GLOBAL, CS_PATH_BINNED, CS_PATH_BINNED_NOCOMBINE = 0, 1, 2, 3, 4
 
 _STATUS_NAMES = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ENOMEM", -3: "CS_EDOMAIN", -4: "CS_EOVERFLOW",
                  -5: "CS_EDEVICE", -6: "CS_EBUSY"}

@@ -254,11 +254,19 @@ static cs_status check_dtypes(cs_dtype kt, cs_dtype wt, int* kb, int* wb) {
   return CS_OK;
 }
 
-static bool binned_fits(const cs_sketch* s, uint32_t* log2g) {
-  uint32_t lg = s->log2m > kRangeLog2 ? s->log2m - kRangeLog2 : 0;
+// Range width R = 2^log2r for the two-pass update: at most 32 ranges per row
+// while R <= 2^14 (pass-2 LDS table of R int64), never below 2^11.
+static bool binned_fits(const cs_sketch* s, uint32_t* log2g, uint32_t* log2r) {
+  // up to 2^18 buckets: 8-16 ranges per row (wave tiles); beyond: 32 or more (block tiles)
+  uint32_t lr = s->log2m <= 18 ? (s->log2m > 3 ? s->log2m - 3 : 0) : (s->log2m > 5 ? s->log2m - 5 : 0);
+  lr = std::max(lr, kMinRangeLog2);
+  lr = std::min(lr, kMaxRangeLog2);
+  lr = std::min(lr, s->log2m);
+  uint32_t lg = s->log2m - lr;
   if (lg > kMaxLog2g) return false;
-  if (((uint64_t)s->rows << lg) + (1u << lg) + 1 > 16000) return false;  // pass-1 LDS counters
+  if (((uint64_t)s->rows << lg) + (1u << lg) + 2 > 8192) return false;  // pass-1 LDS counters
   *log2g = lg;
+  *log2r = lr;
   return true;
 }
 
@@ -268,11 +276,12 @@ UpdatePlan mcs::plan_update(const cs_sketch* s, uint64_t n) {
   const uint64_t tile = (uint64_t)kBlock * kKeysPerThread;
   const uint64_t tiles = (n + tile - 1) / tile;
   UpdatePlan p{};
-  uint32_t log2g = 0;
+  uint32_t log2g = 0, log2r = 0;
   int path = s->path;
-  if (path == 0) path = cells * 8 <= kLdsTableMax ? CS_PATH_LDS : binned_fits(s, &log2g) ? CS_PATH_BINNED : CS_PATH_GLOBAL;
+  if (path == 0)
+    path = cells * 8 <= kLdsTableMax ? CS_PATH_LDS : binned_fits(s, &log2g, &log2r) ? CS_PATH_BINNED : CS_PATH_GLOBAL;
   if (path == CS_PATH_LDS && cells * 8 > kLdsTableMax) path = CS_PATH_GLOBAL;
-  if (path == CS_PATH_BINNED && !binned_fits(s, &log2g)) path = CS_PATH_GLOBAL;
+  if (path == CS_PATH_BINNED && !binned_fits(s, &log2g, &log2r)) path = CS_PATH_GLOBAL;
   if (path == CS_PATH_LDS) {
     p.variant = kVariantLds;
     p.lds_bytes = (uint32_t)(cells * 8);
@@ -282,8 +291,20 @@ UpdatePlan mcs::plan_update(const cs_sketch* s, uint64_t n) {
   } else if (path == CS_PATH_BINNED) {
     p.variant = kVariantBinned;
     p.log2g = log2g;
+    p.log2r = log2r;
+    p.dedup = s->combine;
     const uint32_t G = 1u << log2g;
-    p.lds_bytes = (uint32_t)(((uint64_t)s->rows * G + G + 1) * 4);
+    p.wave_tiles = G <= 16 && s->rows <= 16;
+    if (p.wave_tiles)
+      p.lds_bytes = (kBlock / 64) * (p.dedup ? binw_lds_per_wave_host<true>(s->rows, G)
+                                             : binw_lds_per_wave_host<false>(s->rows, G));
+    else
+      p.lds_bytes = (p.dedup ? bin_lds_fixed_bytes<true>() : bin_lds_fixed_bytes<false>()) +
+                    (uint32_t)(((uint64_t)s->rows * G + G + 2) * 4);
+    const uint32_t span = 1u << std::min(log2r, s->log2m);
+    p.acc_lds_bytes = span * 8;
+    const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(2, kLdsPerCu / p.acc_lds_bytes));
+    p.acc_blocks = (uint32_t)(dev.cus * per_cu);
   } else {
     p.variant = kVariantGlobal;
     p.lds_bytes = 0;
@@ -332,20 +353,23 @@ cs_status mcs::enqueue_update(cs_sketch* s, const UpdatePlan& plan, const void* 
   if (plan.variant == kVariantBinned) {
     const DeviceInfo& dev = device_info(s->device);
     const uint32_t G = 1u << plan.log2g;
+    const uint64_t tk = plan.wave_tiles ? kWaveTile : kBinTile;
     const uint64_t chunk = std::min<uint64_t>(n, kBinChunkKeys);
-    const uint64_t tiles_c = (chunk + kBinTile - 1) / kBinTile;
-    const size_t rec_bytes = (size_t)tiles_c * s->rows * kBinTile * 4;
+    const uint64_t tiles_c = (chunk + tk - 1) / tk;
+    const size_t rec_bytes = (size_t)tiles_c * s->rows * tk * 4;
     const size_t desc_bytes = (size_t)tiles_c * s->rows * (G + 1) * 4;
     cs_status st = ensure_workspace(s, rec_bytes + desc_bytes);
     if (st != CS_OK) return st;
     for (uint64_t off = 0; off < n; off += chunk) {
       const uint64_t len = std::min<uint64_t>(chunk, n - off);
       UpdatePlan p = plan;
-      p.tiles = (uint32_t)((len + kBinTile - 1) / kBinTile);
-      p.blocks = (uint32_t)std::min<uint64_t>(p.tiles, (uint64_t)dev.cus * 8);
+      p.tiles = (uint32_t)((len + tk - 1) / tk);
+      const uint64_t tiles_per_block = plan.wave_tiles ? kBlock / 64 : 1;
+      p.blocks = (uint32_t)std::min<uint64_t>((p.tiles + tiles_per_block - 1) / tiles_per_block, (uint64_t)dev.cus * 8);
+      // pass-2 items: enough (partition, slice) pairs to keep every block busy
       const uint64_t parts = (uint64_t)s->rows << plan.log2g;
-      uint64_t slices = (2ull * dev.cus + parts - 1) / parts;
-      slices = std::max<uint64_t>(1, std::min<uint64_t>(slices, p.tiles / 8 ? p.tiles / 8 : 1));
+      uint64_t slices = (4ull * plan.acc_blocks + parts - 1) / parts;
+      slices = std::max<uint64_t>(1, std::min<uint64_t>(slices, std::max<uint64_t>(1, p.tiles / 64)));
       p.acc_slices = (uint32_t)slices;
       p.recs = (uint32_t*)s->d_work;
       p.desc = (uint32_t*)((char*)s->d_work + rec_bytes);
@@ -372,8 +396,9 @@ cs_status mcs::enqueue_update(cs_sketch* s, const UpdatePlan& plan, const void* 
 
 extern "C" cs_status cs_set_update_path(cs_sketch* s, int path) {
   if (!s) return fail(CS_EINVAL, "sketch is NULL");
-  if (path < CS_PATH_AUTO || path > CS_PATH_BINNED) return fail(CS_EINVAL, "unknown update path %d", path);
-  s->path = path;
+  if (path < CS_PATH_AUTO || path > CS_PATH_BINNED_NOCOMBINE) return fail(CS_EINVAL, "unknown update path %d", path);
+  s->path = path == CS_PATH_BINNED_NOCOMBINE ? CS_PATH_BINNED : path;
+  s->combine = path != CS_PATH_BINNED_NOCOMBINE;
   return CS_OK;
 }
 

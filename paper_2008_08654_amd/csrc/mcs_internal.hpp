@@ -26,6 +26,7 @@ struct cs_sketch {
   void* d_work = nullptr;          // workspace of the two-pass update (bins)
   size_t work_bytes = 0;
   int path = 0;                    // 0 auto, else forced cs_update path (CS_PATH_*)
+  bool combine = true;             // two-pass update combines repeated keys of a tile
 };
 
 namespace mcs {

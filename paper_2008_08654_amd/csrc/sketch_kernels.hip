@@ -18,38 +18,59 @@ namespace mcs {
 // ---------------------------------------------------------------------------
 // hashing of one key in one row
 // ---------------------------------------------------------------------------
-template <int K>
-__device__ __forceinline__ uint64_t hash61_x32(const uint4* __restrict__ c, uint32_t x) {
-  F61 y{c[K - 1].x, c[K - 1].y};
+// A row's coefficients, read once per row and kept in scalar registers
+// (readfirstlane): all lanes hash with the same polynomial.
+template <int K, int NP>
+struct RowCoeffs {
+  uint32_t w[NP * K][3];
+};
+
+template <int K, int NP>
+__device__ __forceinline__ RowCoeffs<K, NP> load_row_coeffs(const uint4* __restrict__ c) {
+  RowCoeffs<K, NP> rc;
 #pragma unroll
-  for (int i = K - 2; i >= 0; --i) y = p61_step_x32(y, x, F61{c[i].x, c[i].y});
+  for (int i = 0; i < NP * K; ++i) {
+    const uint4 v = c[i];
+    rc.w[i][0] = __builtin_amdgcn_readfirstlane(v.x);
+    rc.w[i][1] = __builtin_amdgcn_readfirstlane(v.y);
+    rc.w[i][2] = __builtin_amdgcn_readfirstlane(v.z);
+  }
+  return rc;
+}
+
+template <int K, int NP>
+__device__ __forceinline__ uint64_t hash61_x32(const RowCoeffs<K, NP>& c, int q, uint32_t x) {
+  F61 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
+#pragma unroll
+  for (int i = K - 2; i >= 0; --i) y = p61_step_x32(y, x, F61{c.w[q * K + i][0], c.w[q * K + i][1]});
   return p61_final(y);
 }
 
-template <int K>
-__device__ __forceinline__ uint64_t hash61_x64(const uint4* __restrict__ c, uint32_t x0, uint32_t x1) {
-  F61 y{c[K - 1].x, c[K - 1].y};
+template <int K, int NP>
+__device__ __forceinline__ uint64_t hash61_x64(const RowCoeffs<K, NP>& c, int q, uint32_t x0, uint32_t x1) {
+  F61 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
 #pragma unroll
-  for (int i = K - 2; i >= 0; --i) y = p61_step_x64(y, x0, x1, F61{c[i].x, c[i].y});
+  for (int i = K - 2; i >= 0; --i) y = p61_step_x64(y, x0, x1, F61{c.w[q * K + i][0], c.w[q * K + i][1]});
   return p61_final(y);
 }
 
-template <int K>
-__device__ __forceinline__ F89 hash89(const uint4* __restrict__ c, uint32_t x0, uint32_t x1) {
-  F89 y{c[K - 1].x, c[K - 1].y, c[K - 1].z};
+template <int K, int NP>
+__device__ __forceinline__ F89 hash89(const RowCoeffs<K, NP>& c, int q, uint32_t x0, uint32_t x1) {
+  F89 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1], c.w[q * K + K - 1][2]};
 #pragma unroll
-  for (int i = K - 2; i >= 0; --i) y = p89_step(y, x0, x1, F89{c[i].x, c[i].y, c[i].z});
+  for (int i = K - 2; i >= 0; --i)
+    y = p89_step(y, x0, x1, F89{c.w[q * K + i][0], c.w[q * K + i][1], c.w[q * K + i][2]});
   return p89_final(y);
 }
 
-// Bucket and sign bit of key (x0, x1) in the row whose first coefficient
-// record is `c`.  WIDE selects the two-limb key path for p61.
-template <int PRIME, int MODE, int K, bool WIDE>
-__device__ __forceinline__ void bucket_sign(const uint4* __restrict__ c, uint32_t x0, uint32_t x1,
-                                            uint32_t log2m, uint32_t& bucket, uint32_t& a) {
+// Bucket and sign bit of key (x0, x1) under a row's coefficients.  WIDE
+// selects the two-limb key path for p61.
+template <int PRIME, int MODE, int K, bool WIDE, int NP>
+__device__ __forceinline__ void bucket_sign(const RowCoeffs<K, NP>& c, uint32_t x0, uint32_t x1, uint32_t log2m,
+                                            uint32_t& bucket, uint32_t& a) {
   const uint32_t mask = (1u << log2m) - 1u;
   if constexpr (PRIME == kPrime61) {
-    uint64_t h = WIDE ? hash61_x64<K>(c, x0, x1) : hash61_x32<K>(c, x0);
+    uint64_t h = WIDE ? hash61_x64<K, NP>(c, 0, x0, x1) : hash61_x32<K, NP>(c, 0, x0);
     if constexpr (MODE == kTwoForOne) {
       a = (uint32_t)h & 1u;
       bucket = ((uint32_t)h >> 1) & mask;
@@ -57,12 +78,12 @@ __device__ __forceinline__ void bucket_sign(const uint4* __restrict__ c, uint32_
       a = (uint32_t)(h >> 60) & 1u;
       bucket = (uint32_t)h & mask;
     } else {
-      uint64_t h2 = WIDE ? hash61_x64<K>(c + K, x0, x1) : hash61_x32<K>(c + K, x0);
+      uint64_t h2 = WIDE ? hash61_x64<K, NP>(c, 1, x0, x1) : hash61_x32<K, NP>(c, 1, x0);
       a = (uint32_t)h2 & 1u;
       bucket = (uint32_t)h & mask;
     }
   } else {
-    F89 h = hash89<K>(c, x0, x1);
+    F89 h = hash89<K, NP>(c, 0, x0, x1);
     if constexpr (MODE == kTwoForOne) {
       a = h.w0 & 1u;
       bucket = (h.w0 >> 1) & mask;
@@ -70,7 +91,7 @@ __device__ __forceinline__ void bucket_sign(const uint4* __restrict__ c, uint32_
       a = (h.w2 >> 24) & 1u;
       bucket = h.w0 & mask;
     } else {
-      F89 h2 = hash89<K>(c + K, x0, x1);
+      F89 h2 = hash89<K, NP>(c, 1, x0, x1);
       a = h2.w0 & 1u;
       bucket = h.w0 & mask;
     }
@@ -138,20 +159,20 @@ __global__ __launch_bounds__(kBlock) void k_update_lds(UpdateArgs<KeyT, WT> args
     // wave-uniform choice of the one-limb key path (all keys < 2^32)
     const bool wide = PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0);
     for (uint32_t r = 0; r < args.rows; ++r) {
-      const uint4* c = args.coeffs + (size_t)r * NP * K;
+      const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
       unsigned long long* row = lds + ((size_t)r << args.log2m);
       if (wide) {
 #pragma unroll
         for (int j = 0; j < kKpt; ++j) {
           uint32_t bk, a;
-          bucket_sign<PRIME, MODE, K, true>(c, x0[j], x1[j], args.log2m, bk, a);
+          bucket_sign<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m, bk, a);
           if (ok[j]) atomicAdd(&row[bk], signed_weight(wv[j], a));
         }
       } else {
 #pragma unroll
         for (int j = 0; j < kKpt; ++j) {
           uint32_t bk, a;
-          bucket_sign<PRIME, MODE, K, false>(c, x0[j], x1[j], args.log2m, bk, a);
+          bucket_sign<PRIME, MODE, K, false, NP>(c, x0[j], x1[j], args.log2m, bk, a);
           if (ok[j]) atomicAdd(&row[bk], signed_weight(wv[j], a));
         }
       }
@@ -196,15 +217,15 @@ __global__ __launch_bounds__(kBlock) void k_update_global(UpdateArgs<KeyT, WT> a
     if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;
     const bool wide = PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0);
     for (uint32_t r = 0; r < args.rows; ++r) {
-      const uint4* c = args.coeffs + (size_t)r * NP * K;
+      const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
       unsigned long long* row = args.table + ((size_t)r << args.log2m);
 #pragma unroll
       for (int j = 0; j < kKpt; ++j) {
         uint32_t bk, a;
         if (wide)
-          bucket_sign<PRIME, MODE, K, true>(c, x0[j], x1[j], args.log2m, bk, a);
+          bucket_sign<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m, bk, a);
         else
-          bucket_sign<PRIME, MODE, K, false>(c, x0[j], x1[j], args.log2m, bk, a);
+          bucket_sign<PRIME, MODE, K, false, NP>(c, x0[j], x1[j], args.log2m, bk, a);
         if (ok[j]) atomicAdd(&row[bk], signed_weight(wv[j], a));
       }
     }
@@ -215,31 +236,69 @@ __global__ __launch_bounds__(kBlock) void k_update_global(UpdateArgs<KeyT, WT> a
 // ---------------------------------------------------------------------------
 // Two-pass update for tables larger than LDS.
 //
+// The m buckets of a row are cut into G = m / R ranges of R = 2^log2r
+// buckets; (row, range) is a partition.
 // Pass 1 (k_bin): each block takes tiles of kBinTile keys.  For every row it
-// hashes the tile's keys, and writes one 4-byte record per key into the
-// tile's region for that row, grouped by bucket range g = bucket >> 14
-// (partition (row, g)).  A record is (bucket & (2^14-1)) << 18 | (signed
-// weight & (2^18-1)); a signed weight outside [-2^17, 2^17) goes straight to
-// the global table with an atomic instead.  desc[tile][row][0..G] holds the
-// offsets of the groups inside the region (G = number of ranges per row).
-//
-// Pass 2 (k_accumulate): block (slice, partition) adds the records of its
-// partition from a slice of tiles into an int64 LDS table of 2^14 counters
-// and then adds the non-zero counters into the global table.
+// hashes the tile's keys and writes one 4-byte record per key into the
+// tile's region for that row, grouped by range.  A record is
+// (bucket mod R) << wbits | (signed weight mod 2^wbits), wbits = 32 - log2r;
+// a signed weight outside [-2^(wbits-1), 2^(wbits-1)) is added to the global
+// table directly with an atomic instead.  desc[tile][row][0..G] holds the
+// offsets of the groups in the region.
+// Pass 2 (k_accumulate): persistent blocks take (partition, slice of tiles)
+// items, add the item's records into an int64 LDS table of R counters, then
+// add the non-zero counters into the global table with coalesced atomics.
 // ---------------------------------------------------------------------------
-template <int PRIME, int MODE, int K, typename KeyT, typename WT>
+
+// Exclusive prefix of in[0..G) into out[0..G] by one wave (out[G] = total).
+__device__ __forceinline__ void wave_exclusive_scan(const uint32_t* in, uint32_t* out, uint32_t G, uint32_t lane) {
+  uint32_t carry = 0;
+  for (uint32_t b = 0; b < G; b += 64) {
+    const uint32_t v0 = b + lane < G ? in[b + lane] : 0u;
+    uint32_t v = v0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      uint32_t t = __shfl_up(v, d, 64);
+      if (lane >= (uint32_t)d) v += t;
+    }
+    if (b + lane < G) out[b + lane] = carry + v - v0;
+    carry += __shfl(v, 63, 64);
+  }
+  if (lane == 0) out[G] = carry;
+}
+
+__device__ __forceinline__ uint32_t dedup_slot(uint32_t x0, uint32_t x1) {
+  return (x0 * 0x9E3779B1u) ^ (x1 * 0x85EBCA77u) ^ (x0 >> 15);
+}
+
+// LDS layout of k_bin: [combining: keys u64[T] | weights i64[T] | slots
+// u32[2T]] | stage u32[T] | hist u32[rows*G] | offs u32[G+1] | spare u32
+// (bin_lds_fixed_bytes() covers the parts before hist).
+template <int PRIME, int MODE, int K, typename KeyT, typename WT, bool DEDUP>
 __global__ __launch_bounds__(kBlock) void k_bin(BinArgs<KeyT, WT> args) {
-  extern __shared__ uint32_t sh[];
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr uint32_t T = kBinTile;
+  unsigned long long* skey = (unsigned long long*)smem;          // DEDUP
+  long long* swt = (long long*)(smem + T * 8);                    // DEDUP
+  uint32_t* slots = (uint32_t*)(smem + T * 16);                   // DEDUP, 2T entries
+  uint32_t* stage = (uint32_t*)(smem + (DEDUP ? T * 24 : 0));
+  uint32_t* hist = stage + T;
   const uint32_t G = 1u << args.log2g;
-  uint32_t* hist = sh;                 // rows x G
-  uint32_t* offs = sh + args.rows * G; // G + 1
+  uint32_t* offs = hist + args.rows * G;
+  uint32_t* count = offs + G + 1;
+  const uint32_t log2r = args.log2r, wbits = 32u - log2r;
   constexpr int kKpt = kBinKpt;
   constexpr int NP = MODE == kTwoPoly ? 2 : 1;
-  const uint32_t rmask = (1u << kRangeLog2) - 1u;
+  const uint32_t rmask = (1u << log2r) - 1u;
+  const uint32_t wmask = (1u << wbits) - 1u;
+  const int64_t half = 1ll << (wbits - 1);
+  const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t bad = 0;
   for (uint32_t tile = blockIdx.x; tile < args.tiles; tile += gridDim.x) {
     for (uint32_t i = threadIdx.x; i < args.rows * G; i += kBlock) hist[i] = 0;
-    const uint64_t base = (uint64_t)tile * kBinTile;
+    if (DEDUP)
+      for (uint32_t i = threadIdx.x; i < 2 * T; i += kBlock) slots[i] = 0;
+    const uint64_t base = (uint64_t)tile * T;
     uint32_t x0[kKpt], x1[kKpt];
     int64_t wv[kKpt];
     bool ok[kKpt];
@@ -258,24 +317,100 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs<KeyT, WT> args) {
 #pragma unroll
     for (int j = 0; j < kKpt; ++j) any_hi |= x1[j];
     if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;
+    if constexpr (DEDUP) {
+      // Combine repeated keys of the tile: C[i(x)] += s(x) * sum of their
+      // weights is the same update (the sketch is linear).
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j) {
+        const uint32_t idx = j * kBlock + threadIdx.x;
+        skey[idx] = ((unsigned long long)x1[j] << 32) | x0[j];
+        swt[idx] = wv[j];
+      }
+      __syncthreads();
+      uint32_t own = 0;  // bit j: key j is the first copy in the tile
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j) {
+        if (!ok[j]) continue;
+        const uint32_t idx = j * kBlock + threadIdx.x;
+        const unsigned long long key = ((unsigned long long)x1[j] << 32) | x0[j];
+        uint32_t h = dedup_slot(x0[j], x1[j]) & (2 * T - 1);
+        for (uint32_t probe = 0; probe < 2 * T; ++probe) {
+          const uint32_t cur = atomicCAS(&slots[h], 0u, idx + 1);
+          if (cur == 0) {
+            own |= 1u << j;
+            break;
+          }
+          if (skey[cur - 1] == key) {
+            atomicAdd((unsigned long long*)&swt[cur - 1], (unsigned long long)wv[j]);
+            break;
+          }
+          h = (h + 1) & (2 * T - 1);
+        }
+      }
+      __syncthreads();
+      // compact the first copies (with their summed weights) to the front
+      unsigned long long ck[kKpt];
+      long long cw[kKpt];
+      uint32_t mine = 0;
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j) {
+        const uint32_t idx = j * kBlock + threadIdx.x;
+        ck[j] = skey[idx];
+        cw[j] = swt[idx];
+        mine += (own >> j) & 1u;
+      }
+      uint32_t v = mine;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v += t;
+      }
+      if (lane == 63) stage[wave] = v;  // stage is free until the row loop
+      __syncthreads();
+      uint32_t pos = v - mine;
+      uint32_t total = 0;
+      for (uint32_t w = 0; w < kBlock / 64; ++w) {
+        const uint32_t c = stage[w];
+        if (w < wave) pos += c;
+        total += c;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j)
+        if ((own >> j) & 1u) {
+          skey[pos] = ck[j];
+          swt[pos] = cw[j];
+          ++pos;
+        }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j) {
+        const uint32_t e = j * kBlock + threadIdx.x;
+        ok[j] = e < total;
+        const unsigned long long key = ok[j] ? skey[e] : 0ull;
+        x0[j] = (uint32_t)key;
+        x1[j] = (uint32_t)(key >> 32);
+        wv[j] = ok[j] ? swt[e] : 0;
+      }
+    }
     const bool wide = PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0);
     __syncthreads();
     for (uint32_t r = 0; r < args.rows; ++r) {
-      const uint4* c = args.coeffs + (size_t)r * NP * K;
+      const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
       uint32_t rec[kKpt], grp[kKpt], tick[kKpt];
 #pragma unroll
       for (int j = 0; j < kKpt; ++j) {
         uint32_t bk, a;
         if (wide)
-          bucket_sign<PRIME, MODE, K, true>(c, x0[j], x1[j], args.log2m, bk, a);
+          bucket_sign<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m, bk, a);
         else
-          bucket_sign<PRIME, MODE, K, false>(c, x0[j], x1[j], args.log2m, bk, a);
+          bucket_sign<PRIME, MODE, K, false, NP>(c, x0[j], x1[j], args.log2m, bk, a);
         int64_t sw = a ? -wv[j] : wv[j];
-        grp[j] = bk >> kRangeLog2;
-        rec[j] = ((bk & rmask) << kRecWeightBits) | ((uint32_t)sw & ((1u << kRecWeightBits) - 1u));
-        const bool fits = (uint64_t)(sw + (1ll << (kRecWeightBits - 1))) < (1ull << kRecWeightBits);
+        grp[j] = bk >> log2r;
+        rec[j] = ((bk & rmask) << wbits) | ((uint32_t)sw & wmask);
+        const bool fits = (uint64_t)(sw + half) < (2ull * (uint64_t)half);
         tick[j] = 0xffffffffu;
-        if (ok[j]) {
+        if (ok[j] && sw != 0) {
           if (fits)
             tick[j] = atomicAdd(&hist[r * G + grp[j]], 1u);
           else
@@ -283,52 +418,306 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs<KeyT, WT> args) {
         }
       }
       __syncthreads();
-      // exclusive prefix over the row's G group counts
-      uint32_t* d = args.desc + ((size_t)tile * args.rows + r) * (G + 1);
-      for (uint32_t g = threadIdx.x; g <= G; g += kBlock) {
-        uint32_t acc = 0;
-        for (uint32_t q = 0; q < g; ++q) acc += hist[r * G + q];
-        offs[g] = acc;
-        d[g] = acc;
+      if (wave == 0) {
+        wave_exclusive_scan(hist + r * G, offs, G, lane);
+        uint32_t* d = args.desc + ((size_t)tile * args.rows + r) * (G + 1);
+        for (uint32_t g = lane; g <= G; g += 64) d[g] = offs[g];
       }
       __syncthreads();
-      uint32_t* out = args.recs + ((size_t)tile * args.rows + r) * kBinTile;
 #pragma unroll
       for (int j = 0; j < kKpt; ++j)
-        if (tick[j] != 0xffffffffu) out[offs[grp[j]] + tick[j]] = rec[j];
+        if (tick[j] != 0xffffffffu) stage[offs[grp[j]] + tick[j]] = rec[j];
+      __syncthreads();
+      // coalesced copy of the row's records to the tile region
+      const uint32_t nrec = offs[G];
+      uint4* out = (uint4*)(args.recs + ((size_t)tile * args.rows + r) * T);
+      const uint4* st4 = (const uint4*)stage;
+      for (uint32_t q = threadIdx.x; q * 4 < nrec; q += kBlock) out[q] = st4[q];
       __syncthreads();
     }
+  }
+  (void)count;
+  if (bad) atomicOr(args.flags, kFlagDomain);
+}
+
+// Wave-level LDS ordering point: every LDS access of the wave issued before
+// it is complete and visible to the wave's other lanes after it.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Pass 1 with one tile of kWaveTile keys per wave (for G <= 16 ranges per
+// row): tickets, prefix sums, key combining and staging are wave-local, so
+// the kernel has no block barriers.  Same record and descriptor format as
+// k_bin with tiles of kWaveTile keys.
+template <bool DEDUP>
+__host__ __device__ constexpr uint32_t binw_lds_per_wave(uint32_t rows, uint32_t G) {
+  // [combining: keys u64[T] | weights i64[T]] | slots u32[2T] (stage aliases it) | hist u32[rows*G]
+  return (DEDUP ? kWaveTile * 16 : 0) + 2 * kWaveTile * 4 + rows * G * 4;
+}
+
+// Rows of one wave tile: hash every slot straight-line (no branches, so the
+// slots' Horner chains interleave), take tickets for record-sized weights,
+// prefix the group counts, stage the records in sorted order and copy them
+// out with 16-byte stores.
+template <int PRIME, int MODE, int K, int NP, bool WIDE, int kKpt, typename BA>
+__device__ __forceinline__ void bin_rows_wave(const BA& args, uint32_t tile, uint32_t G, uint32_t lane, uint32_t* hist,
+                                              uint32_t* stage, const uint32_t (&x0)[kKpt], const uint32_t (&x1)[kKpt],
+                                              const int64_t (&wv)[kKpt], const uint32_t (&wpos)[kKpt],
+                                              const uint32_t (&wneg)[kKpt], uint32_t use, uint32_t esc, bool any_esc) {
+  const uint32_t log2r = args.log2r, wbits = 32u - log2r;
+  const uint32_t rmask = (1u << log2r) - 1u;
+  for (uint32_t r = 0; r < args.rows; ++r) {
+    const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
+    uint32_t bk[kKpt], a[kKpt];
+#pragma unroll
+    for (int j = 0; j < kKpt; ++j) bucket_sign<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m, bk[j], a[j]);
+    uint32_t rec[kKpt], grp[kKpt], tick[kKpt];
+#pragma unroll
+    for (int j = 0; j < kKpt; ++j) {
+      grp[j] = bk[j] >> log2r;
+      rec[j] = ((bk[j] & rmask) << wbits) | (a[j] ? wneg[j] : wpos[j]);
+      tick[j] = 0xffffffffu;
+      if ((use >> j) & 1u) tick[j] = atomicAdd(&hist[r * G + grp[j]], 1u);
+    }
+    if (any_esc) {  // weights too large for a record go straight to the table
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j)
+        if ((esc >> j) & 1u) {
+          const int64_t sw = a[j] ? -wv[j] : wv[j];
+          atomicAdd(&args.table[((size_t)r << args.log2m) + bk[j]], (unsigned long long)sw);
+        }
+    }
+    wave_lds_sync();
+    // exclusive prefix over the G <= 16 group counts inside the first 16-lane
+    // DPP row (row_shr 1, 2, 4, 8): lane g holds off[g]
+    const uint32_t cg = lane < G ? hist[r * G + lane] : 0u;
+    uint32_t v = cg;
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);
+    const uint32_t off = v - cg;
+    const uint32_t nrec = __builtin_amdgcn_readlane(v, G - 1);
+    uint32_t* d = args.desc + ((size_t)tile * args.rows + r) * (G + 1);
+    if (lane < G) d[lane] = off;
+    if (lane == G) d[G] = nrec;
+#pragma unroll
+    for (int j = 0; j < kKpt; ++j) {
+      const uint32_t o = __shfl(off, grp[j] & 15u, 64);
+      if (tick[j] != 0xffffffffu) stage[o + tick[j]] = rec[j];
+    }
+    wave_lds_sync();
+    uint4* out = (uint4*)(args.recs + ((size_t)tile * args.rows + r) * kWaveTile);
+    const uint4* st4 = (const uint4*)stage;
+    for (uint32_t q = lane; q * 4 < nrec; q += 64) out[q] = st4[q];
+    wave_lds_sync();
+  }
+}
+
+template <int PRIME, int MODE, int K, typename KeyT, typename WT, bool DEDUP>
+__global__ __launch_bounds__(kBlock) void k_bin_wave(BinArgs<KeyT, WT> args) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr uint32_t T = kWaveTile;
+  constexpr int kKpt = T / 64;
+  constexpr int NP = MODE == kTwoPoly ? 2 : 1;
+  const uint32_t G = 1u << args.log2g;
+  // wave index made explicitly uniform so the tile loop, the row loop and the
+  // coefficient loads stay scalar
+  const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned char* mine = smem + (size_t)wave * binw_lds_per_wave<DEDUP>(args.rows, G);
+  unsigned long long* skey = (unsigned long long*)mine;
+  long long* swt = (long long*)(mine + T * 8);
+  uint32_t* slots = (uint32_t*)(mine + (DEDUP ? T * 16 : 0));
+  uint32_t* stage = slots;  // reused once the combining table is no longer needed
+  uint32_t* hist = slots + 2 * T;
+  const uint32_t log2r = args.log2r, wbits = 32u - log2r;
+  const uint32_t rmask = (1u << log2r) - 1u;
+  const uint32_t wmask = (1u << wbits) - 1u;
+  const int64_t half = 1ll << (wbits - 1);
+  uint32_t bad = 0;
+  const uint32_t nw = gridDim.x * (kBlock / 64);
+  for (uint32_t tile = blockIdx.x * (kBlock / 64) + wave; tile < args.tiles; tile += nw) {
+    for (uint32_t i = lane; i < args.rows * G; i += 64) hist[i] = 0;
+    if (DEDUP)
+      for (uint32_t i = lane; i < 2 * T; i += 64) slots[i] = 0;
+    const uint64_t base = (uint64_t)tile * T;
+    uint32_t x0[kKpt], x1[kKpt];
+    int64_t wv[kKpt];
+    bool ok[kKpt];
+#pragma unroll
+    for (int j = 0; j < kKpt; ++j) {
+      uint64_t i = base + (uint64_t)j * 64 + lane;
+      ok[j] = i < args.n;
+      x0[j] = x1[j] = 0;
+      wv[j] = 0;
+      if (ok[j]) {
+        load_key(args.keys, i, x0[j], x1[j]);
+        wv[j] = load_weight(args.weights, i);
+      }
+    }
+    uint32_t any_hi = 0;
+#pragma unroll
+    for (int j = 0; j < kKpt; ++j) any_hi |= x1[j];
+    if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;
+    if constexpr (DEDUP) {
+      // Combine repeated keys of the tile (exact: the sketch is linear).
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j) {
+        const uint32_t idx = j * 64 + lane;
+        skey[idx] = ((unsigned long long)x1[j] << 32) | x0[j];
+        swt[idx] = wv[j];
+      }
+      wave_lds_sync();
+      uint32_t own = 0;
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j) {
+        if (!ok[j]) continue;
+        const uint32_t idx = j * 64 + lane;
+        const unsigned long long key = ((unsigned long long)x1[j] << 32) | x0[j];
+        uint32_t h = dedup_slot(x0[j], x1[j]) & (2 * T - 1);
+        for (uint32_t probe = 0; probe < 2 * T; ++probe) {
+          const uint32_t cur = atomicCAS(&slots[h], 0u, idx + 1);
+          if (cur == 0) {
+            own |= 1u << j;
+            break;
+          }
+          if (skey[cur - 1] == key) {
+            atomicAdd((unsigned long long*)&swt[cur - 1], (unsigned long long)wv[j]);
+            break;
+          }
+          h = (h + 1) & (2 * T - 1);
+        }
+      }
+      wave_lds_sync();
+      unsigned long long ck[kKpt];
+      long long cw[kKpt];
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j) {
+        const uint32_t idx = j * 64 + lane;
+        ck[j] = skey[idx];
+        cw[j] = swt[idx];
+        cnt += (own >> j) & 1u;
+      }
+      uint32_t v = cnt;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v += t;
+      }
+      const uint32_t total = __shfl(v, 63, 64);
+      uint32_t pos = v - cnt;
+      wave_lds_sync();
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j)
+        if ((own >> j) & 1u) {
+          skey[pos] = ck[j];
+          swt[pos] = cw[j];
+          ++pos;
+        }
+      wave_lds_sync();
+#pragma unroll
+      for (int j = 0; j < kKpt; ++j) {
+        const uint32_t e = j * 64 + lane;
+        ok[j] = e < total;
+        const unsigned long long key = ok[j] ? skey[e] : 0ull;
+        x0[j] = (uint32_t)key;
+        x1[j] = (uint32_t)(key >> 32);
+        wv[j] = ok[j] ? swt[e] : 0;
+      }
+      wave_lds_sync();
+    }
+    const bool wide = PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0);
+    // per key, independent of the row: record-sized weights (both signs fit
+    // the record field) and the weight's field for both signs
+    uint32_t use = 0, esc = 0;  // bit j: key j goes into a record / is added directly
+    uint32_t wpos[kKpt], wneg[kKpt];
+#pragma unroll
+    for (int j = 0; j < kKpt; ++j) {
+      const bool small = wv[j] > -half && wv[j] < half;
+      use |= (ok[j] && wv[j] != 0 && small ? 1u : 0u) << j;
+      esc |= (ok[j] && !small ? 1u : 0u) << j;
+      wpos[j] = (uint32_t)wv[j] & wmask;
+      wneg[j] = (uint32_t)(-wv[j]) & wmask;
+    }
+    const bool any_esc = __any(esc != 0);
+    if (wide)
+      bin_rows_wave<PRIME, MODE, K, NP, true, kKpt>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
+    else
+      bin_rows_wave<PRIME, MODE, K, NP, false, kKpt>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
   }
   if (bad) atomicOr(args.flags, kFlagDomain);
 }
 
 __global__ __launch_bounds__(kAccBlock) void k_accumulate(AccArgs args) {
-  __shared__ unsigned long long acc[1u << kRangeLog2];
+  extern __shared__ unsigned long long acc[];
   const uint32_t G = 1u << args.log2g;
-  const uint32_t part = blockIdx.y;  // row * G + g
-  const uint32_t r = part >> args.log2g, g = part & (G - 1);
-  const uint32_t R = 1u << kRangeLog2;
-  for (uint32_t i = threadIdx.x; i < R; i += kAccBlock) acc[i] = 0;
-  __syncthreads();
-  const uint32_t per = (args.tiles + gridDim.x - 1) / gridDim.x;
-  const uint32_t t0 = blockIdx.x * per, t1 = min(args.tiles, t0 + per);
-  const uint32_t wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = kAccBlock / 64;
-  for (uint32_t tile = t0 + wave; tile < t1; tile += nw) {
-    const uint32_t* d = args.desc + ((size_t)tile * args.rows + r) * (G + 1) + g;
-    const uint32_t b = d[0], e = d[1];
-    const uint32_t* rec = args.recs + ((size_t)tile * args.rows + r) * kBinTile;
-    for (uint32_t i = b + lane; i < e; i += 64) {
-      uint32_t v = rec[i];
-      int64_t sw = (int64_t)((int32_t)(v << (32 - kRecWeightBits)) >> (32 - kRecWeightBits));
-      atomicAdd(&acc[v >> kRecWeightBits], (unsigned long long)sw);
+  const uint32_t log2r = args.log2r, wbits = 32u - log2r;
+  const uint32_t span = args.log2m < log2r ? (1u << args.log2m) : (1u << log2r);  // counters per range
+  const uint32_t items = (args.rows << args.log2g) * args.slices;
+  const uint32_t per = (args.tiles + args.slices - 1) / args.slices;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
+  const uint32_t nw = kAccBlock / 64;
+  constexpr int kU = 8;  // tiles in flight per wave
+  for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
+    const uint32_t part = item / args.slices, slice = item % args.slices;
+    const uint32_t r = part >> args.log2g, g = part & (G - 1);
+    for (uint32_t i = threadIdx.x; i < span; i += kAccBlock) acc[i] = 0;
+    __syncthreads();
+    const uint32_t t0 = slice * per, t1 = min(args.tiles, t0 + per);
+    for (uint32_t tb = t0 + wave * 64; tb < t1; tb += nw * 64) {
+      // lane l fetches the group bounds of tile tb + l
+      uint32_t lb = 0, le = 0;
+      if (tb + lane < t1) {
+        const uint32_t* d = args.desc + ((size_t)(tb + lane) * args.rows + r) * (G + 1) + g;
+        lb = d[0];
+        le = d[1];
+      }
+      const uint32_t ntiles = min(64u, t1 - tb);
+      for (uint32_t u0 = 0; u0 < ntiles; u0 += kU) {
+        uint32_t cur[kU], end[kU];
+        const uint32_t* src[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          cur[u] = __shfl(lb, u0 + u, 64);
+          end[u] = u0 + u < ntiles ? __shfl(le, u0 + u, 64) : cur[u];
+          src[u] = args.recs + ((size_t)(tb + u0 + u) * args.rows + r) * args.tile_keys;
+        }
+        bool more = true;
+        while (more) {
+          uint32_t v[kU];
+          bool has[kU];
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const uint32_t idx = cur[u] + lane;
+            has[u] = idx < end[u];
+            v[u] = has[u] ? src[u][idx] : 0u;
+          }
+#pragma unroll
+          for (int u = 0; u < kU; ++u)
+            if (has[u]) {
+              int64_t sw = (int64_t)((int32_t)(v[u] << log2r) >> log2r);
+              atomicAdd(&acc[v[u] >> wbits], (unsigned long long)sw);
+            }
+          more = false;
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            cur[u] += 64;
+            more |= cur[u] < end[u];
+          }
+        }
+      }
     }
-  }
-  __syncthreads();
-  unsigned long long* dst = args.table + ((size_t)r << args.log2m) + ((size_t)g << kRangeLog2);
-  const uint32_t span = args.log2m < kRangeLog2 ? (1u << args.log2m) : R;  // counters of this range
-  for (uint32_t i = threadIdx.x; i < span; i += kAccBlock) {
-    unsigned long long v = acc[i];
-    if (v) atomicAdd(&dst[i], v);
+    __syncthreads();
+    unsigned long long* dst = args.table + ((size_t)r << args.log2m) + ((size_t)g << log2r);
+    for (uint32_t i = threadIdx.x; i < span; i += kAccBlock) {
+      unsigned long long v = acc[i];
+      if (v) atomicAdd(&dst[i], v);
+    }
+    __syncthreads();
   }
 }
 
@@ -347,11 +736,11 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs<KeyT> args) {
   uint32_t rows = args.rows;
   for (uint32_t r = 0; r < rows; ++r) {
     uint32_t bk, a;
-    const uint4* c = args.coeffs + (size_t)r * NP * K;
+    const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
     if (PRIME == kPrime61 && x1 != 0)
-      bucket_sign<PRIME, MODE, K, true>(c, x0, x1, args.log2m, bk, a);
+      bucket_sign<PRIME, MODE, K, true, NP>(c, x0, x1, args.log2m, bk, a);
     else
-      bucket_sign<PRIME, MODE, K, false>(c, x0, x1, args.log2m, bk, a);
+      bucket_sign<PRIME, MODE, K, false, NP>(c, x0, x1, args.log2m, bk, a);
     int64_t v = args.table[((size_t)r << args.log2m) + bk];
     v = a ? (int64_t)(0ull - (uint64_t)v) : v;
     // insertion into the sorted prefix
@@ -469,14 +858,31 @@ __global__ void k_fill_zero(unsigned long long* __restrict__ dst, uint64_t n) {
 template <int PRIME, int MODE, int K, typename KeyT, typename WT>
 static hipError_t launch_update_t(const UpdatePlan& plan, const UpdateArgs<KeyT, WT>& a, hipStream_t st) {
   if (plan.variant == kVariantBinned) {
-    BinArgs<KeyT, WT> b{a.keys, a.weights, a.n, a.coeffs, a.rows, a.log2m, plan.log2g, plan.tiles,
+    BinArgs<KeyT, WT> b{a.keys, a.weights, a.n, a.coeffs, a.rows, a.log2m, plan.log2g, plan.log2r, plan.tiles,
                         plan.recs, plan.desc, a.table, a.flags};
-    hipLaunchKernelGGL((k_bin<PRIME, MODE, K, KeyT, WT>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, b);
+    static bool attr_set = false;  // dynamic LDS above 64 KiB needs the kernel attribute
+    if (!attr_set) {
+      (void)hipFuncSetAttribute((const void*)k_accumulate, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(unsigned long long) << kMaxRangeLog2));
+      (void)hipFuncSetAttribute((const void*)k_bin<PRIME, MODE, K, KeyT, WT, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      attr_set = true;
+    }
+    if (plan.wave_tiles) {
+      if (plan.dedup)
+        hipLaunchKernelGGL((k_bin_wave<PRIME, MODE, K, KeyT, WT, true>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, b);
+      else
+        hipLaunchKernelGGL((k_bin_wave<PRIME, MODE, K, KeyT, WT, false>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, b);
+    } else if (plan.dedup) {
+      hipLaunchKernelGGL((k_bin<PRIME, MODE, K, KeyT, WT, true>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, b);
+    } else {
+      hipLaunchKernelGGL((k_bin<PRIME, MODE, K, KeyT, WT, false>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, b);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    AccArgs c{plan.recs, plan.desc, plan.tiles, a.rows, a.log2m, plan.log2g, a.table};
-    const uint32_t parts = a.rows << plan.log2g;
-    hipLaunchKernelGGL(k_accumulate, dim3(plan.acc_slices, parts), dim3(kAccBlock), 0, st, c);
+    AccArgs c{plan.recs, plan.desc, plan.tiles, a.rows, a.log2m, plan.log2g, plan.log2r, plan.acc_slices,
+              plan.wave_tiles ? kWaveTile : kBinTile, a.table};
+    hipLaunchKernelGGL(k_accumulate, dim3(plan.acc_blocks), dim3(kAccBlock), plan.acc_lds_bytes, st, c);
     return hipGetLastError();
   }
   if (plan.variant == kVariantLds) {

@@ -31,11 +31,12 @@ constexpr int kVariantBinned = 2;
 
 // two-pass (binned) update
 constexpr int kBinKpt = 8;                          // keys per thread in a pass-1 tile
-constexpr uint32_t kBinTile = kBlock * kBinKpt;     // keys per tile
-constexpr uint32_t kRangeLog2 = 14;                 // counters per partition (int64 LDS table in pass 2)
-constexpr uint32_t kRecWeightBits = 18;             // signed weight field of a record
+constexpr uint32_t kBinTile = kBlock * kBinKpt;     // keys per tile (block tiles)
+constexpr uint32_t kWaveTile = 512;                 // keys per tile (wave tiles, <= 16 ranges per row)
+constexpr uint32_t kMinRangeLog2 = 11;              // counters per partition: 2^11 .. 2^14 (int64 LDS in pass 2)
+constexpr uint32_t kMaxRangeLog2 = 14;
 constexpr int kAccBlock = 1024;                     // pass-2 block (16 wave64s)
-constexpr uint32_t kMaxLog2g = 8;                   // at most 256 ranges per row
+constexpr uint32_t kMaxLog2g = 10;                  // at most 1024 ranges per row
 
 struct UpdatePlan {
   int variant;
@@ -43,8 +44,13 @@ struct UpdatePlan {
   uint32_t lds_bytes;
   // binned variant
   uint32_t log2g;       // log2 of bucket ranges per row
+  uint32_t log2r;       // log2 of buckets per range
   uint32_t tiles;       // tiles in this launch
-  uint32_t acc_slices;  // pass-2 blocks per partition
+  uint32_t acc_slices;  // pass-2 items per partition
+  uint32_t acc_blocks;  // pass-2 persistent blocks
+  uint32_t acc_lds_bytes;
+  bool dedup;           // combine repeated keys of a tile before hashing
+  bool wave_tiles;      // pass 1 with one tile per wave (k_bin_wave)
   uint32_t* recs;       // [tiles][rows][kBinTile]
   uint32_t* desc;       // [tiles][rows][G + 1]
 };
@@ -90,6 +96,7 @@ struct BinArgs {
   uint32_t rows;
   uint32_t log2m;
   uint32_t log2g;
+  uint32_t log2r;
   uint32_t tiles;
   uint32_t* recs;
   uint32_t* desc;
@@ -104,6 +111,9 @@ struct AccArgs {
   uint32_t rows;
   uint32_t log2m;
   uint32_t log2g;
+  uint32_t log2r;
+  uint32_t slices;
+  uint32_t tile_keys;
   unsigned long long* table;
 };
 
@@ -141,6 +151,17 @@ struct EstPartial {
 };
 
 hipError_t launch_update(const UpdatePlan& plan, const UpdateArgsAny& a, hipStream_t st);
+
+template <bool DEDUP>
+constexpr uint32_t binw_lds_per_wave_host(uint32_t rows, uint32_t G) {
+  return (DEDUP ? kWaveTile * 16 : 0) + 2 * kWaveTile * 4 + rows * G * 4;
+}
+
+// LDS bytes of the pass-1 kernel besides the per-row counters
+template <bool DEDUP>
+constexpr uint32_t bin_lds_fixed_bytes() {
+  return (DEDUP ? (kBinTile * 8 + kBinTile * 8 + 2 * kBinTile * 4) : 0) + kBinTile * 4;
+}
 hipError_t launch_query(const QueryArgsAny& a, hipStream_t st);
 hipError_t launch_estimate(const int64_t* table, uint32_t rows, uint32_t log2m, uint32_t slices, EstPartial* part,
                            int64_t* out, uint32_t* flags, hipStream_t st);

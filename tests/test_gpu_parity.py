@@ -110,7 +110,7 @@ def test_large_table_zipf_two_for_one_and_two_poly():
         _check_sketch(sk, keys, w)
 
 
-@pytest.mark.parametrize("path", [2, 3])
+@pytest.mark.parametrize("path", [2, 3, 4])
 @pytest.mark.parametrize("rows,log2m,prime,mode", [
     (9, 16, 1, 0), (9, 16, 1, 2), (5, 20, 2, 0), (64, 10, 1, 1), (3, 15, 2, 2), (2, 22, 1, 0)])
 def test_forced_paths_match_oracle(path, rows, log2m, prime, mode):
@@ -125,6 +125,9 @@ def test_forced_paths_match_oracle(path, rows, log2m, prime, mode):
     w[2::89] = -(1 << 17)
     w[3::89] = (1 << 17) - 1
     w[4::89] = -(1 << 17) + 1
+    w[5::89] = 1 << 20
+    w[6::89] = -(1 << 20)
+    w[7::89] = (1 << 20) - 1
     keys, w = keys.to(DEV), w.to(DEV)
     sk = _make(rows, 1 << log2m, prime, seed=500 + log2m, mode=mode)
     sk.set_update_path(path)
@@ -135,6 +138,24 @@ def test_forced_paths_match_oracle(path, rows, log2m, prime, mode):
                               O.coeffs_from_seed(PRIMES[prime], rows, mode, seed=500 + log2m),
                               _u64(keys[: n // 3]), w[: n // 3].cpu().numpy(), table=want)
     _check_sketch(sk, keys, w, table=want)
+
+
+@pytest.mark.parametrize("path", [3, 4])
+def test_combining_repeated_keys_exact(path):
+    """Heavy repetition inside tiles, weights that cancel to zero, and combined weights
+    too large for a record: the two-pass update stays exact."""
+    n = 5 * 2048 + 17
+    keys = W.uniform_u64(3, n) & ((1 << 60) - 1)
+    keys[::3] = 12345            # one key on a third of the stream
+    keys[1::7] = (1 << 59) + 1   # another on a seventh
+    w = W.bounded_int(3, n, -100, 100)
+    w[::3] = torch.tensor([5, -5]).repeat(n)[: w[::3].numel()]  # cancels in pairs
+    w[1::7] = 1 << 19            # sums far beyond the record field
+    keys, w = keys.to(DEV), w.to(DEV)
+    sk = _make(7, 1 << 17, M.CS_P61, seed=71)
+    sk.set_update_path(path)
+    sk.update(keys, w)
+    _check_sketch(sk, keys, w)
 
 
 def test_lds_path_forced_on_small_table():
