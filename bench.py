@@ -16,6 +16,9 @@ Other workloads (--workload) measure the other kernels the same way:
   small_table_u32              t=5, m=2^10 (table in LDS), uint32 uniform keys, int64 weights = 1
   p89_uniform                  p = 2^89-1, t=5, m=2^20, 2^26 uint64 uniform keys, int64 weights = 1
   divmod_p61 / divmod_p89 / divmod_p64_59   2^28 values uniform in [0, p^2)
+  batched                      4096 sketches (t=5, m=2^e, e uniform in 8..16, seeds 4000+i), stream
+                               lengths floor(2^U(8,22)), uint64 Zipf(1.1) keys, int32 weights in
+                               [-100,100]: one batched update (autotuned, HIP graph) vs 4096 cs_update
 Prints one JSON line.  --gpus N > 1 exits: this build measures one GPU.
 """
 from __future__ import annotations
@@ -178,6 +181,117 @@ def run_sketch(args, wl):
     return out
 
 
+def _log(msg):
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
+def run_batched(args):
+    import numpy as np
+    import torch
+    import paper_2008_08654_amd as M
+    import workloads as W
+
+    count = args.n or 4096
+    dev = torch.device("cuda:0")
+    seed = W.DATA_SEED + 4
+    lens = W.loguniform_int(seed, count, 8.0, 22.0)
+    log2m = W.bounded_int(seed, count, 8, 16, stream=6)
+    total = int(lens.sum())
+    offs = [0] + np.cumsum(lens.numpy()).tolist()
+    t_gen = time.perf_counter()
+    keys = torch.empty(total, dtype=torch.int64, device=dev)
+    w = torch.empty(total, dtype=torch.int32, device=dev)
+    step_gen = 1 << 27
+    for o in range(0, total, step_gen):  # chunked generation bounds the temporaries
+        nn = min(step_gen, total - o)
+        kk, ww = W.stream_zipf_u64(nn, device=dev, seed=seed + 1 + o // step_gen)
+        keys[o:o + nn] = kk
+        w[o:o + nn] = ww
+        del kk, ww
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    _log(f"batched: {count} members, {total} keys generated in {t_gen:.1f} s")
+    sketches = [M.Sketch(5, 1 << int(log2m[i]), prime=M.CS_P61, seed=4000 + i) for i in range(count)]
+    members = [(sketches[i], keys[offs[i]:offs[i + 1]], w[offs[i]:offs[i + 1]]) for i in range(count)]
+    batch = M.Batch(members)
+    stream = torch.cuda.current_stream()
+    t_tune = time.perf_counter()
+    chosen = batch.autotune(stream)
+    t_tune = time.perf_counter() - t_tune
+    _log(f"batched: autotuned in {t_tune:.1f} s -> lds_table_max {chosen.lds_table_max}, "
+         f"chunk {chosen.lds_chunk_keys}, combine {chosen.combine}")
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, sum(a.elapsed_time(b) for a, b in ev) / steps
+
+    L = M.lib()
+    sp = M._stream(None)
+    handles = [(sk.handle, ctypes.c_void_p(k.data_ptr()), ctypes.c_void_p(ww.data_ptr()), k.numel())
+               for sk, k, ww in members]
+
+    def plain():
+        for h, kp, wp, n in handles:
+            if n:
+                M._check(L.cs_update(h, kp, M.CS_U64, wp, M.CS_I32, n, sp))
+
+    elapsed, batch_ms = timed(batch.update, args.steps)
+    _log(f"batched: {args.steps} batched steps, {elapsed * 1e3 / args.steps:.2f} ms each")
+    plain_elapsed, plain_ms = timed(plain, max(1, args.steps // 4))
+    _log(f"batched: plain per-sketch launches, {plain_elapsed * 1e3 / max(1, args.steps // 4):.2f} ms per pass")
+    plain_wall_ms = plain_elapsed * 1e3 / max(1, args.steps // 4)
+    ops_key = 5 * OPS_PER_KEY_ROW[("p61", 0)] + OPS_PER_KEY
+    achieved = ops_key * total / (batch_ms * 1e-3) / 1e12
+    ng, nl, nt = batch.classes()
+    out = {"metric": "aggregate Gkeys/s into 4096 Count Sketches (p=2^61-1, 4-universal), one batched update",
+           "value": round(total * args.steps / elapsed / 1e9, 3), "unit": "Gkeys/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "batched", "sketches": count, "keys": total, "rows": 5,
+                      "buckets": "2^8..2^16 log-uniform", "classes": {"direct_atomics": ng, "lds": nl,
+                                                                      "two_pass": nt},
+                      "autotuned": {"lds_table_max": chosen.lds_table_max, "lds_chunk_keys": chosen.lds_chunk_keys,
+                                    "combine": chosen.combine}, "autotune_s": round(t_tune, 2),
+                      "plain_launches_ms": round(plain_wall_ms, 3),
+                      "plain_gkeys_per_s": round(total / (plain_wall_ms * 1e-3) / 1e9, 3),
+                      "batched_vs_plain_speedup": round(plain_wall_ms / (elapsed * 1e3 / args.steps), 2),
+                      "input_generation_s": round(t_gen, 2)},
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                        "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                        "kernel": "batched update (all launches)", "kernel_avg_ms": round(batch_ms, 4),
+                        "algorithmic_ops_per_key": ops_key}}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        t0 = time.perf_counter()
+        done = 0
+        i = 0
+        while time.perf_counter() - t0 < 15.0 and i < count:
+            sk, k, ww = members[i]
+            if k.numel():
+                c = O.coeffs_from_seed(O.PRIME_P61, 5, O.TWO_FOR_ONE, 4000 + i)
+                O.cs_update(O.PRIME_P61, O.TWO_FOR_ONE, 5, 1 << int(log2m[i]), c, k.cpu().numpy().view(np.uint64),
+                            ww.cpu().numpy().astype(np.int64))
+                done += k.numel()
+            i += 1
+        dt = time.perf_counter() - t0
+        _log(f"batched: oracle sample of {i} members done")
+        out["cpu_baseline"] = {"value": round(done / dt / 1e9, 6), "unit": "Gkeys/s", "cores": 5, "kind": "oracle",
+                               "sample": f"first {i} members ({done} keys), {dt:.1f} s, one thread per row"}
+    for sk in sketches:
+        sk.close()
+    batch.close()
+    return out
+
+
 def run_divmod(args, wl):
     import numpy as np
     import torch
@@ -241,7 +355,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="single_stream_zipf", choices=sorted(SKETCH_WORKLOADS) + sorted(DIVMOD_WORKLOADS))
+    ap.add_argument("--workload", default="single_stream_zipf",
+                    choices=sorted(SKETCH_WORKLOADS) + sorted(DIVMOD_WORKLOADS) + ["batched"])
     ap.add_argument("--n", type=int, default=None, help="override the number of keys / values")
     ap.add_argument("--path", type=int, default=0, help="force an update path (1 LDS, 2 global, 3 binned)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -251,7 +366,9 @@ def main():
         print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one GPU "
               f"(the sketch shards by key range plus one int64 all-reduce, not built here)", file=sys.stderr)
         sys.exit(2)
-    if args.workload in SKETCH_WORKLOADS:
+    if args.workload == "batched":
+        out = run_batched(args)
+    elif args.workload in SKETCH_WORKLOADS:
         out = run_sketch(args, SKETCH_WORKLOADS[args.workload])
     else:
         out = run_divmod(args, DIVMOD_WORKLOADS[args.workload])

@@ -1,0 +1,71 @@
+/*
+ * mcs_batch.h -- batched Count Sketch update: many independent sketches
+ * (same prime, mode and polynomial degree; each with its own coefficients,
+ * table size and stream) updated by a few persistent launches instead of one
+ * launch per sketch.  Each sketch's result is exactly what cs_update on that
+ * sketch alone gives (Algorithm 2, Process, for every key of its stream).
+ * Needs mcs.h.
+ */
+#ifndef MCS_BATCH_H
+#define MCS_BATCH_H
+
+#include "mcs.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One member of a batch: the sketch and its stream (device pointers, n keys
+ * and n weights).  The pointers are kept by the batch: every cs_batch_update
+ * reads the current contents of the same buffers. */
+typedef struct {
+  cs_sketch* sketch;
+  const void* keys;
+  const void* weights;
+  uint64_t n;
+} cs_batch_item;
+
+/* Tuning knobs (0 = default).  A sketch is updated
+ *   - with direct device-scope atomics when n < buckets/8 (fewer updates than
+ *     a table flush would cost),
+ *   - in LDS when rows*buckets*8 <= lds_table_max (default 65536, at most
+ *     163840),
+ *   - else with the two-pass update (buckets <= 2^18 and rows <= 16 here).
+ * lds_chunk_keys: keys per LDS work item (default 65536).
+ * combine: the two-pass update combines repeated keys inside tiles (default 1;
+ *   set -1 to disable).
+ * use_graph: capture the launches once into a HIP graph and replay it
+ *   (default 1; set -1 to disable). */
+typedef struct {
+  uint32_t lds_table_max;
+  uint32_t lds_chunk_keys;
+  int combine;
+  int use_graph;
+} cs_batch_options;
+
+typedef struct cs_batch cs_batch;
+
+/* Builds a batch over `count` items.  All sketches must live on the current
+ * device and share prime, mode and k; key_type / weight_type apply to every
+ * item.  opts may be NULL.  Allocates the batch's descriptors and workspace
+ * (freed by cs_batch_destroy); the sketches stay owned by the caller and must
+ * outlive the batch. */
+cs_status cs_batch_create(const cs_batch_item* items, uint32_t count, cs_dtype key_type, cs_dtype weight_type,
+                          const cs_batch_options* opts, cs_batch** out);
+/* Enqueues one update of every member on `stream` (adds each stream into its
+ * sketch, as cs_update would). */
+cs_status cs_batch_update(cs_batch* b, hipStream_t stream);
+/* Tries candidate options on the real batch, keeps the fastest and writes it
+ * to *chosen (may be NULL).  The trial runs add into the members' tables:
+ * they are zeroed (cs_reset) when it returns.  Synchronises `stream`. */
+cs_status cs_batch_autotune(cs_batch* b, hipStream_t stream, cs_batch_options* chosen);
+cs_status cs_batch_get_options(const cs_batch* b, cs_batch_options* out);
+/* Counts of members per update class: direct atomics, LDS, two-pass. */
+cs_status cs_batch_classes(const cs_batch* b, uint32_t* n_global, uint32_t* n_lds, uint32_t* n_twopass);
+/* Waits for the batch's work and frees it.  NULL is accepted. */
+void cs_batch_destroy(cs_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCS_BATCH_H */

@@ -65,6 +65,11 @@ def lib() -> ctypes.CDLL:
             "mersenne_mod": [i32, P, u64, P, P],
             "mersenne_divmod_naive": [i32, P, u64, P, P, P],
             "mersenne_status": [P],
+            "cs_batch_create": [P, u32, i32, i32, P, P],
+            "cs_batch_update": [P, P],
+            "cs_batch_autotune": [P, P, P],
+            "cs_batch_get_options": [P, P],
+            "cs_batch_classes": [P, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -72,6 +77,8 @@ def lib() -> ctypes.CDLL:
             f.restype = i32
         L.cs_destroy.argtypes = [P]
         L.cs_destroy.restype = None
+        L.cs_batch_destroy.argtypes = [P]
+        L.cs_batch_destroy.restype = None
         L.cs_last_error.restype = ctypes.c_char_p
         L.cs_version.restype = ctypes.c_char_p
         _lib = L
@@ -210,6 +217,77 @@ class Sketch:
 
     def sync(self, stream=None):
         _check(lib().cs_sync(self._h, _stream(stream)))
+
+
+class _BatchItem(ctypes.Structure):
+    _fields_ = [("sketch", ctypes.c_void_p), ("keys", ctypes.c_void_p), ("weights", ctypes.c_void_p),
+                ("n", ctypes.c_uint64)]
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("lds_table_max", ctypes.c_uint32), ("lds_chunk_keys", ctypes.c_uint32),
+                ("combine", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+class Batch:
+    """Owning handle of a cs_batch over (sketch, keys, weights) members (include/mcs_batch.h)."""
+
+    def __init__(self, members, options: BatchOptions | None = None):
+        if not members:
+            raise ValueError("empty batch")
+        items = (_BatchItem * len(members))()
+        kt = wt = None
+        self._keep = []
+        for i, (sk, keys, weights) in enumerate(members):
+            if keys.numel() != weights.numel():
+                raise ValueError("keys and weights differ in length")
+            k_dt = _key_dtype(keys) if keys.numel() else (kt if kt is not None else CS_U64)
+            w_dt = _weight_dtype(weights) if weights.numel() else (wt if wt is not None else CS_I64)
+            if kt is None:
+                kt, wt = k_dt, w_dt
+            elif keys.numel() and (k_dt != kt or w_dt != wt):
+                raise ValueError("all members must share key and weight dtypes")
+            items[i].sketch = sk.handle.value
+            items[i].keys = keys.data_ptr() if keys.numel() else None
+            items[i].weights = weights.data_ptr() if weights.numel() else None
+            items[i].n = keys.numel()
+            self._keep.append((sk, keys, weights))
+        self._h = ctypes.c_void_p()
+        _check(lib().cs_batch_create(items, len(members), kt, wt,
+                                     ctypes.byref(options) if options is not None else None, ctypes.byref(self._h)))
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def update(self, stream=None):
+        _check(lib().cs_batch_update(self._h, _stream(stream)))
+
+    def autotune(self, stream=None) -> BatchOptions:
+        out = BatchOptions()
+        _check(lib().cs_batch_autotune(self._h, _stream(stream), ctypes.byref(out)))
+        return out
+
+    def options(self) -> BatchOptions:
+        out = BatchOptions()
+        _check(lib().cs_batch_get_options(self._h, ctypes.byref(out)))
+        return out
+
+    def classes(self) -> tuple[int, int, int]:
+        a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().cs_batch_classes(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def close(self):
+        if self._h:
+            lib().cs_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mersenne_divmod(prime: int, x, quot=None, rem=None, stream=None, naive: bool = False):

@@ -296,8 +296,8 @@ UpdatePlan mcs::plan_update(const cs_sketch* s, uint64_t n) {
     const uint32_t G = 1u << log2g;
     p.wave_tiles = G <= 16 && s->rows <= 16;
     if (p.wave_tiles)
-      p.lds_bytes = (kBlock / 64) * (p.dedup ? binw_lds_per_wave_host<true>(s->rows, G)
-                                             : binw_lds_per_wave_host<false>(s->rows, G));
+      p.lds_bytes = (kBlock / 64) * (p.dedup ? binw_lds_per_wave<true>(s->rows, G)
+                                             : binw_lds_per_wave<false>(s->rows, G));
     else
       p.lds_bytes = (p.dedup ? bin_lds_fixed_bytes<true>() : bin_lds_fixed_bytes<false>()) +
                     (uint32_t)(((uint64_t)s->rows * G + G + 2) * 4);

@@ -124,15 +124,15 @@ __device__ __forceinline__ unsigned long long signed_weight(int64_t w, uint32_t 
 // table, processes a contiguous key range, then adds the non-zero partial
 // counters into the global table with coalesced int64 atomics.
 // ---------------------------------------------------------------------------
+// Zero the block's LDS table, add keys [begin, end) of `args` into it, then add
+// its non-zero counters into args.table.  Used by the single-sketch and the
+// batched kernels.
 template <int PRIME, int MODE, int K, typename KeyT, typename WT>
-__global__ __launch_bounds__(kBlock) void k_update_lds(UpdateArgs<KeyT, WT> args) {
-  extern __shared__ unsigned long long lds[];
+__device__ __forceinline__ void lds_block_update(const UpdateArgs<KeyT, WT>& args, uint64_t begin, uint64_t end,
+                                                 unsigned long long* lds) {
   const uint32_t cells = args.rows << args.log2m;
   for (uint32_t i = threadIdx.x; i < cells; i += kBlock) lds[i] = 0;
   __syncthreads();
-
-  const uint64_t begin = (uint64_t)blockIdx.x * args.keys_per_block;
-  const uint64_t end = min(args.n, begin + args.keys_per_block);
   constexpr int kKpt = kKeysPerThread;
   constexpr int NP = MODE == kTwoPoly ? 2 : 1;
   uint32_t bad = 0;
@@ -186,13 +186,19 @@ __global__ __launch_bounds__(kBlock) void k_update_lds(UpdateArgs<KeyT, WT> args
   }
 }
 
+template <int PRIME, int MODE, int K, typename KeyT, typename WT>
+__global__ __launch_bounds__(kBlock) void k_update_lds(UpdateArgs<KeyT, WT> args) {
+  extern __shared__ unsigned long long lds[];
+  const uint64_t begin = (uint64_t)blockIdx.x * args.keys_per_block;
+  const uint64_t end = min(args.n, begin + args.keys_per_block);
+  lds_block_update<PRIME, MODE, K, KeyT, WT>(args, begin, end, lds);
+}
+
 // ---------------------------------------------------------------------------
 // Table in global memory, one device-scope int64 atomic per (key, row).
 // ---------------------------------------------------------------------------
 template <int PRIME, int MODE, int K, typename KeyT, typename WT>
-__global__ __launch_bounds__(kBlock) void k_update_global(UpdateArgs<KeyT, WT> args) {
-  const uint64_t begin = (uint64_t)blockIdx.x * args.keys_per_block;
-  const uint64_t end = min(args.n, begin + args.keys_per_block);
+__device__ __forceinline__ void global_block_update(const UpdateArgs<KeyT, WT>& args, uint64_t begin, uint64_t end) {
   constexpr int kKpt = kKeysPerThread;
   constexpr int NP = MODE == kTwoPoly ? 2 : 1;
   uint32_t bad = 0;
@@ -231,6 +237,13 @@ __global__ __launch_bounds__(kBlock) void k_update_global(UpdateArgs<KeyT, WT> a
     }
   }
   if (bad) atomicOr(args.flags, kFlagDomain);
+}
+
+template <int PRIME, int MODE, int K, typename KeyT, typename WT>
+__global__ __launch_bounds__(kBlock) void k_update_global(UpdateArgs<KeyT, WT> args) {
+  const uint64_t begin = (uint64_t)blockIdx.x * args.keys_per_block;
+  const uint64_t end = min(args.n, begin + args.keys_per_block);
+  global_block_update<PRIME, MODE, K, KeyT, WT>(args, begin, end);
 }
 
 // ---------------------------------------------------------------------------
@@ -452,11 +465,6 @@ __device__ __forceinline__ void wave_lds_sync() {
 // row): tickets, prefix sums, key combining and staging are wave-local, so
 // the kernel has no block barriers.  Same record and descriptor format as
 // k_bin with tiles of kWaveTile keys.
-template <bool DEDUP>
-__host__ __device__ constexpr uint32_t binw_lds_per_wave(uint32_t rows, uint32_t G) {
-  // [combining: keys u64[T] | weights i64[T]] | slots u32[2T] (stage aliases it) | hist u32[rows*G]
-  return (DEDUP ? kWaveTile * 16 : 0) + 2 * kWaveTile * 4 + rows * G * 4;
-}
 
 // Rows of one wave tile: hash every slot straight-line (no branches, so the
 // slots' Horner chains interleave), take tickets for record-sized weights,
@@ -517,17 +525,15 @@ __device__ __forceinline__ void bin_rows_wave(const BA& args, uint32_t tile, uin
   }
 }
 
+// One wave tile of pass 1 (kWaveTile keys of `args`, wave-local LDS `mine`).
+// Returns domain-error bits.
 template <int PRIME, int MODE, int K, typename KeyT, typename WT, bool DEDUP>
-__global__ __launch_bounds__(kBlock) void k_bin_wave(BinArgs<KeyT, WT> args) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ uint32_t bin_wave_tile(const BinArgs<KeyT, WT>& args, uint32_t tile, uint32_t lane,
+                                                  unsigned char* mine) {
   constexpr uint32_t T = kWaveTile;
   constexpr int kKpt = T / 64;
   constexpr int NP = MODE == kTwoPoly ? 2 : 1;
   const uint32_t G = 1u << args.log2g;
-  // wave index made explicitly uniform so the tile loop, the row loop and the
-  // coefficient loads stay scalar
-  const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  unsigned char* mine = smem + (size_t)wave * binw_lds_per_wave<DEDUP>(args.rows, G);
   unsigned long long* skey = (unsigned long long*)mine;
   long long* swt = (long long*)(mine + T * 8);
   uint32_t* slots = (uint32_t*)(mine + (DEDUP ? T * 16 : 0));
@@ -538,8 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_wave(BinArgs<KeyT, WT> args) {
   const uint32_t wmask = (1u << wbits) - 1u;
   const int64_t half = 1ll << (wbits - 1);
   uint32_t bad = 0;
-  const uint32_t nw = gridDim.x * (kBlock / 64);
-  for (uint32_t tile = blockIdx.x * (kBlock / 64) + wave; tile < args.tiles; tile += nw) {
+  {
     for (uint32_t i = lane; i < args.rows * G; i += 64) hist[i] = 0;
     if (DEDUP)
       for (uint32_t i = lane; i < 2 * T; i += 64) slots[i] = 0;
@@ -648,22 +653,36 @@ __global__ __launch_bounds__(kBlock) void k_bin_wave(BinArgs<KeyT, WT> args) {
       bin_rows_wave<PRIME, MODE, K, NP, true, kKpt>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
     else
       bin_rows_wave<PRIME, MODE, K, NP, false, kKpt>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
-  }
+    }
+  return bad;
+}
+
+template <int PRIME, int MODE, int K, typename KeyT, typename WT, bool DEDUP>
+__global__ __launch_bounds__(kBlock) void k_bin_wave(BinArgs<KeyT, WT> args) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  // wave index made explicitly uniform so the tile loop, the row loop and the
+  // coefficient loads stay scalar
+  const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned char* mine = smem + (size_t)wave * binw_lds_per_wave<DEDUP>(args.rows, 1u << args.log2g);
+  const uint32_t nw = gridDim.x * (kBlock / 64);
+  uint32_t bad = 0;
+  for (uint32_t tile = blockIdx.x * (kBlock / 64) + wave; tile < args.tiles; tile += nw)
+    bad |= bin_wave_tile<PRIME, MODE, K, KeyT, WT, DEDUP>(args, tile, lane, mine);
   if (bad) atomicOr(args.flags, kFlagDomain);
 }
 
-__global__ __launch_bounds__(kAccBlock) void k_accumulate(AccArgs args) {
-  extern __shared__ unsigned long long acc[];
+// One pass-2 item: records of partition `part` from the tiles of slice
+// `slice`, accumulated in LDS `acc` and added into args.table.
+__device__ __forceinline__ void accumulate_item(const AccArgs& args, uint32_t part, uint32_t slice,
+                                                unsigned long long* acc) {
   const uint32_t G = 1u << args.log2g;
   const uint32_t log2r = args.log2r, wbits = 32u - log2r;
   const uint32_t span = args.log2m < log2r ? (1u << args.log2m) : (1u << log2r);  // counters per range
-  const uint32_t items = (args.rows << args.log2g) * args.slices;
   const uint32_t per = (args.tiles + args.slices - 1) / args.slices;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   const uint32_t nw = kAccBlock / 64;
   constexpr int kU = 8;  // tiles in flight per wave
-  for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
-    const uint32_t part = item / args.slices, slice = item % args.slices;
+  {
     const uint32_t r = part >> args.log2g, g = part & (G - 1);
     for (uint32_t i = threadIdx.x; i < span; i += kAccBlock) acc[i] = 0;
     __syncthreads();
@@ -718,7 +737,14 @@ __global__ __launch_bounds__(kAccBlock) void k_accumulate(AccArgs args) {
       if (v) atomicAdd(&dst[i], v);
     }
     __syncthreads();
-  }
+    }
+}
+
+__global__ __launch_bounds__(kAccBlock) void k_accumulate(AccArgs args) {
+  extern __shared__ unsigned long long acc[];
+  const uint32_t items = (args.rows << args.log2g) * args.slices;
+  for (uint32_t item = blockIdx.x; item < items; item += gridDim.x)
+    accumulate_item(args, item / args.slices, item % args.slices, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -850,6 +876,151 @@ __global__ void k_add_tables(unsigned long long* __restrict__ dst, const unsigne
 __global__ void k_fill_zero(unsigned long long* __restrict__ dst, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     dst[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Batched update: many independent sketches (same prime, mode and k) in one
+// launch per pass.  Every work item is (sketch, keys), so a wave always hashes
+// with one sketch's coefficients.
+//   k_batch_lds:  items (sketch, key range) of sketches whose table fits LDS
+//   k_batch_bin:  pass 1 over the wave tiles of all segments of a round;
+//                 a wave finds its segment by binary search on tile_begin
+//   k_batch_acc:  pass 2 items (segment, partition, slice)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T* p) {
+  // all lanes read the same record; copy it through readfirstlane
+  T v = *p;
+  uint32_t* w = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  return v;
+}
+
+template <int PRIME, int MODE, int K, typename KeyT, typename WT>
+__global__ __launch_bounds__(kBlock) void k_batch_lds(const BatchSketch* __restrict__ sks,
+                                                      const BatchLdsItem* __restrict__ items, uint32_t nitems) {
+  extern __shared__ unsigned long long lds[];
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BatchLdsItem item = uniform_load(items + it);
+    const BatchSketch sk = uniform_load(sks + item.sketch);
+    UpdateArgs<KeyT, WT> a{(const KeyT*)sk.keys, (const WT*)sk.weights, sk.n, 0, sk.coeffs, sk.rows, sk.log2m,
+                           sk.table, sk.flags};
+    __syncthreads();  // the previous item's flush has read the LDS table
+    lds_block_update<PRIME, MODE, K, KeyT, WT>(a, item.begin, item.end, lds);
+  }
+}
+
+template <int PRIME, int MODE, int K, typename KeyT, typename WT>
+__global__ __launch_bounds__(kBlock) void k_batch_global(const BatchSketch* __restrict__ sks,
+                                                         const BatchLdsItem* __restrict__ items, uint32_t nitems) {
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BatchLdsItem item = uniform_load(items + it);
+    const BatchSketch sk = uniform_load(sks + item.sketch);
+    UpdateArgs<KeyT, WT> a{(const KeyT*)sk.keys, (const WT*)sk.weights, sk.n, 0, sk.coeffs, sk.rows, sk.log2m,
+                           sk.table, sk.flags};
+    global_block_update<PRIME, MODE, K, KeyT, WT>(a, item.begin, item.end);
+  }
+}
+
+template <int PRIME, int MODE, int K, typename KeyT, typename WT, bool DEDUP>
+__global__ __launch_bounds__(kBlock) void k_batch_bin(const BatchSegment* __restrict__ segs, uint32_t nsegs,
+                                                      uint32_t total_tiles, uint32_t lds_per_wave) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned char* mine = smem + (size_t)wave * lds_per_wave;
+  const uint32_t nw = gridDim.x * (kBlock / 64);
+  for (uint32_t gt = blockIdx.x * (kBlock / 64) + wave; gt < total_tiles; gt += nw) {
+    uint32_t lo = 0, hi = nsegs;  // last segment with tile_begin <= gt
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (uniform_load(&segs[mid].tile_begin) <= gt) lo = mid; else hi = mid;
+    }
+    const BatchSegment sg = uniform_load(segs + lo);
+    BinArgs<KeyT, WT> a{(const KeyT*)sg.keys, (const WT*)sg.weights, sg.n, sg.coeffs, sg.rows, sg.log2m, sg.log2g,
+                        sg.log2r, sg.tiles, sg.recs, sg.desc, sg.table, sg.flags};
+    const uint32_t bad = bin_wave_tile<PRIME, MODE, K, KeyT, WT, DEDUP>(a, gt - sg.tile_begin, lane, mine);
+    if (bad) atomicOr(sg.flags, kFlagDomain);
+  }
+}
+
+__global__ __launch_bounds__(kAccBlock) void k_batch_acc(const BatchSegment* __restrict__ segs,
+                                                        const BatchAccItem* __restrict__ items, uint32_t nitems) {
+  extern __shared__ unsigned long long acc[];
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BatchAccItem item = uniform_load(items + it);
+    const BatchSegment sg = uniform_load(segs + item.segment);
+    AccArgs a{sg.recs, sg.desc, sg.tiles, sg.rows, sg.log2m, sg.log2g, sg.log2r, item.slices, kWaveTile, sg.table};
+    accumulate_item(a, item.part, item.slice, acc);
+  }
+}
+
+template <int PRIME, int MODE, int K, typename KeyT, typename WT>
+static hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t st) {
+  if (b.prepare_only) {  // kernel attributes, set once before any launch or graph capture
+    hipError_t e = hipFuncSetAttribute((const void*)k_batch_lds<PRIME, MODE, K, KeyT, WT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_batch_acc, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(unsigned long long) << kMaxRangeLog2));
+    return e;
+  }
+  if (b.lds_items) {
+    hipLaunchKernelGGL((k_batch_lds<PRIME, MODE, K, KeyT, WT>), dim3(b.lds_blocks), dim3(kBlock), b.lds_bytes, st,
+                       b.sketches, b.lds_item_list, b.lds_items);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (b.glb_items) {
+    hipLaunchKernelGGL((k_batch_global<PRIME, MODE, K, KeyT, WT>), dim3(b.glb_blocks), dim3(kBlock), 0, st,
+                       b.sketches, b.glb_item_list, b.glb_items);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  for (uint32_t r = 0; r < b.rounds; ++r) {
+    const BatchRound& rd = b.round_list[r];
+    if (b.dedup)
+      hipLaunchKernelGGL((k_batch_bin<PRIME, MODE, K, KeyT, WT, true>), dim3(b.bin_blocks), dim3(kBlock),
+                         b.bin_lds_bytes, st, rd.segs, rd.nsegs, rd.total_tiles, b.bin_lds_per_wave);
+    else
+      hipLaunchKernelGGL((k_batch_bin<PRIME, MODE, K, KeyT, WT, false>), dim3(b.bin_blocks), dim3(kBlock),
+                         b.bin_lds_bytes, st, rd.segs, rd.nsegs, rd.total_tiles, b.bin_lds_per_wave);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_acc, dim3(b.acc_blocks), dim3(kAccBlock), b.acc_lds_bytes, st, rd.segs, rd.acc_items,
+                       rd.nacc);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int PRIME, int MODE, int K>
+static hipError_t launch_batch_k(const BatchLaunch& b, hipStream_t st) {
+  if (b.key_bytes == 4 && b.weight_bytes == 4) return launch_batch_t<PRIME, MODE, K, uint32_t, int32_t>(b, st);
+  if (b.key_bytes == 4 && b.weight_bytes == 8) return launch_batch_t<PRIME, MODE, K, uint32_t, int64_t>(b, st);
+  if (b.key_bytes == 8 && b.weight_bytes == 4) return launch_batch_t<PRIME, MODE, K, uint64_t, int32_t>(b, st);
+  return launch_batch_t<PRIME, MODE, K, uint64_t, int64_t>(b, st);
+}
+
+template <int PRIME, int MODE>
+static hipError_t launch_batch_m(const BatchLaunch& b, hipStream_t st) {
+  switch (b.k) {
+    case 2: return launch_batch_k<PRIME, MODE, 2>(b, st);
+    case 8: return launch_batch_k<PRIME, MODE, 8>(b, st);
+    default: return launch_batch_k<PRIME, MODE, 4>(b, st);
+  }
+}
+
+hipError_t launch_batch(const BatchLaunch& b, hipStream_t st) {
+  if (b.prime == kPrime61) {
+    if (b.mode == kTwoForOne) return launch_batch_m<kPrime61, kTwoForOne>(b, st);
+    if (b.mode == kTwoForOneMsb) return launch_batch_m<kPrime61, kTwoForOneMsb>(b, st);
+    return launch_batch_m<kPrime61, kTwoPoly>(b, st);
+  }
+  if (b.mode == kTwoForOne) return launch_batch_m<kPrime89, kTwoForOne>(b, st);
+  if (b.mode == kTwoForOneMsb) return launch_batch_m<kPrime89, kTwoForOneMsb>(b, st);
+  return launch_batch_m<kPrime89, kTwoPoly>(b, st);
 }
 
 // ---------------------------------------------------------------------------

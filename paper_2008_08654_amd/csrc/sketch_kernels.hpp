@@ -152,9 +152,69 @@ struct EstPartial {
 
 hipError_t launch_update(const UpdatePlan& plan, const UpdateArgsAny& a, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// batched update
+// ---------------------------------------------------------------------------
+struct BatchSketch {          // a sketch whose table fits LDS
+  const void* keys;
+  const void* weights;
+  uint64_t n;
+  const uint4* coeffs;
+  unsigned long long* table;
+  uint32_t* flags;
+  uint32_t rows, log2m;
+};
+struct BatchLdsItem {         // keys [begin, end) of sketch `sketch`
+  uint32_t sketch, pad;
+  uint64_t begin, end;
+};
+struct BatchSegment {         // keys of one two-pass sketch handled in a round
+  const void* keys;           // first key of the segment
+  const void* weights;
+  uint64_t n;
+  const uint4* coeffs;
+  unsigned long long* table;
+  uint32_t* flags;
+  uint32_t* recs;             // segment's records: [tiles][rows][kWaveTile]
+  uint32_t* desc;             // segment's group offsets: [tiles][rows][G + 1]
+  uint32_t rows, log2m, log2g, log2r;
+  uint32_t tile_begin, tiles; // wave tiles [tile_begin, tile_begin + tiles) of the round
+};
+struct BatchAccItem {
+  uint32_t segment, part, slice, slices;
+};
+struct BatchRound {
+  const BatchSegment* segs;
+  uint32_t nsegs;
+  uint32_t total_tiles;
+  const BatchAccItem* acc_items;
+  uint32_t nacc;
+};
+struct BatchLaunch {
+  int prime, mode, k, key_bytes, weight_bytes;
+  bool dedup;
+  bool prepare_only;  // only set kernel attributes
+  const BatchSketch* sketches;
+  const BatchLdsItem* lds_item_list;
+  uint32_t lds_items, lds_blocks, lds_bytes;
+  const BatchLdsItem* glb_item_list;  // items of sketches updated with direct atomics
+  uint32_t glb_items, glb_blocks;
+  const BatchRound* round_list;  // host array
+  uint32_t rounds;
+  uint32_t bin_blocks, bin_lds_bytes, bin_lds_per_wave;
+  uint32_t acc_blocks, acc_lds_bytes;
+};
+hipError_t launch_batch(const BatchLaunch& b, hipStream_t st);
+
+// LDS bytes of one wave of the wave-tile pass 1:
+//   [combining: keys u64[T] | weights i64[T]] | slots u32[2T] (records are
+//   staged there) | counters u32[rows*G], padded to 16 bytes.
+// Each wave's region starts at wave * this stride, so the stride must keep the
+// 8-byte key/weight arrays (64-bit LDS atomics need natural alignment) and the
+// 16-byte staged copies aligned for every wave, whatever rows * G is.
 template <bool DEDUP>
-constexpr uint32_t binw_lds_per_wave_host(uint32_t rows, uint32_t G) {
-  return (DEDUP ? kWaveTile * 16 : 0) + 2 * kWaveTile * 4 + rows * G * 4;
+__host__ __device__ constexpr uint32_t binw_lds_per_wave(uint32_t rows, uint32_t G) {
+  return (DEDUP ? kWaveTile * 16 : 0) + 2 * kWaveTile * 4 + ((rows * G * 4 + 15u) & ~15u);
 }
 
 // LDS bytes of the pass-1 kernel besides the per-row counters
