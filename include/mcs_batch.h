@@ -26,8 +26,9 @@ typedef struct {
 } cs_batch_item;
 
 /* Tuning knobs (0 = default).  A sketch is updated
- *   - with direct device-scope atomics when n < buckets/8 (fewer updates than
- *     a table flush would cost),
+ *   - with direct device-scope atomics when n < direct_fraction * buckets
+ *     (default 1/8; negative: never), where fewer updates reach the table
+ *     than a per-partition accumulation would have to clear and flush,
  *   - in LDS when rows*buckets*8 <= lds_table_max (default 65536, at most
  *     163840),
  *   - else with the two-pass update (buckets <= 2^18 and rows <= 16 here).
@@ -41,6 +42,7 @@ typedef struct {
   uint32_t lds_chunk_keys;
   int combine;
   int use_graph;
+  double direct_fraction;
 } cs_batch_options;
 
 typedef struct cs_batch cs_batch;
@@ -55,7 +57,8 @@ cs_status cs_batch_create(const cs_batch_item* items, uint32_t count, cs_dtype k
 /* Enqueues one update of every member on `stream` (adds each stream into its
  * sketch, as cs_update would). */
 cs_status cs_batch_update(cs_batch* b, hipStream_t stream);
-/* Tries candidate options on the real batch, keeps the fastest and writes it
+/* Tries candidate options (LDS table limit, LDS chunk, combining, direct
+ * fraction 1/128, 1/8 or 1) on the real batch, keeps the fastest and writes it
  * to *chosen (may be NULL).  The trial runs add into the members' tables:
  * they are zeroed (cs_reset) when it returns.  Synchronises `stream`. */
 cs_status cs_batch_autotune(cs_batch* b, hipStream_t stream, cs_batch_options* chosen);

@@ -70,6 +70,16 @@ def lib() -> ctypes.CDLL:
             "cs_batch_autotune": [P, P, P],
             "cs_batch_get_options": [P, P],
             "cs_batch_classes": [P, P, P, P],
+            "cs_server_create": [i32, i32, u32, i32, i32, P, P],
+            "cs_server_admit": [P, u32, u64, u64, P],
+            "cs_server_evict": [P, u32],
+            "cs_server_submit_update": [P, u32, P, P, u64, P],
+            "cs_server_submit_f2": [P, u32, P],
+            "cs_server_wait": [P, u64, P],
+            "cs_server_drain": [P],
+            "cs_server_read_counters": [P, u32, P],
+            "cs_server_get_stats": [P, P],
+            "cs_server_replay": [P, P, u32, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -79,6 +89,8 @@ def lib() -> ctypes.CDLL:
         L.cs_destroy.restype = None
         L.cs_batch_destroy.argtypes = [P]
         L.cs_batch_destroy.restype = None
+        L.cs_server_destroy.argtypes = [P]
+        L.cs_server_destroy.restype = None
         L.cs_last_error.restype = ctypes.c_char_p
         L.cs_version.restype = ctypes.c_char_p
         _lib = L
@@ -226,7 +238,7 @@ class _BatchItem(ctypes.Structure):
 
 class BatchOptions(ctypes.Structure):
     _fields_ = [("lds_table_max", ctypes.c_uint32), ("lds_chunk_keys", ctypes.c_uint32),
-                ("combine", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("combine", ctypes.c_int), ("use_graph", ctypes.c_int), ("direct_fraction", ctypes.c_double)]
 
 
 class Batch:
@@ -282,6 +294,128 @@ class Batch:
         if self._h:
             lib().cs_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+CS_REQ_UPDATE, CS_REQ_F2 = 0, 1
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("step_keys", ctypes.c_uint64), ("work_bytes", ctypes.c_uint64),
+                ("direct_fraction", ctypes.c_double)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("f2", ctypes.c_int64), ("arrival_ns", ctypes.c_uint64),
+                ("done_ns", ctypes.c_uint64), ("step", ctypes.c_uint64)]
+
+
+class ServerRequest(ctypes.Structure):
+    _fields_ = [("tenant", ctypes.c_uint32), ("kind", ctypes.c_uint32), ("keys", ctypes.c_void_p),
+                ("weights", ctypes.c_void_p), ("n", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_uint64), ("requests", ctypes.c_uint64), ("keys", ctypes.c_uint64),
+                ("resident_bytes", ctypes.c_uint64), ("budget_bytes", ctypes.c_uint64), ("tenants", ctypes.c_uint32)]
+
+
+class Server:
+    """Owning handle of a cs_server (include/mcs_serve.h): tenants, queued update/F2
+    requests and continuous batching on a worker thread of the library."""
+
+    def __init__(self, prime: int = CS_P61, mode: int = CS_TWO_FOR_ONE, k: int = 4, key_type: int = CS_U64,
+                 weight_type: int = CS_I32, hbm_budget: int = 0, step_keys: int = 0, work_bytes: int = 0,
+                 direct_fraction: float = 0.0):
+        opts = ServerOptions(hbm_budget, step_keys, work_bytes, direct_fraction)
+        self._h = ctypes.c_void_p()
+        self._kt, self._wt = key_type, weight_type
+        self._keep = {}  # ticket -> tensors that must stay alive until the update completes
+        self._untracked = []  # tensors of updates without a ticket, released by drain()
+        _check(lib().cs_server_create(prime, mode, k, key_type, weight_type, ctypes.byref(opts),
+                                      ctypes.byref(self._h)))
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def admit(self, rows: int, buckets: int, seed: int) -> int:
+        t = ctypes.c_uint32()
+        _check(lib().cs_server_admit(self._h, rows, buckets, seed, ctypes.byref(t)))
+        return t.value
+
+    def evict(self, tenant: int):
+        _check(lib().cs_server_evict(self._h, tenant))
+
+    def submit_update(self, tenant: int, keys, weights, ticket: bool = False):
+        """Queue an update; keys/weights stay referenced until wait(ticket) (ticket=True)
+        or drain().  Returns the ticket, or None."""
+        if keys.numel() != weights.numel():
+            raise ValueError("keys and weights differ in length")
+        if keys.numel() and (_key_dtype(keys) != self._kt or _weight_dtype(weights) != self._wt):
+            raise ValueError("key or weight dtype differs from the server's")
+        t = ctypes.c_uint64()
+        _check(lib().cs_server_submit_update(self._h, tenant, _dev_ptr(keys) if keys.numel() else None,
+                                             _dev_ptr(weights) if weights.numel() else None, keys.numel(),
+                                             ctypes.byref(t) if ticket else None))
+        if ticket:
+            self._keep[t.value] = (keys, weights)
+            return t.value
+        self._untracked.append((keys, weights))
+        return None
+
+    def submit_f2(self, tenant: int) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().cs_server_submit_f2(self._h, tenant, ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int) -> ServerResult:
+        out = ServerResult()
+        _check(lib().cs_server_wait(self._h, ticket, ctypes.byref(out)))
+        self._keep.pop(ticket, None)
+        return out
+
+    def drain(self):
+        _check(lib().cs_server_drain(self._h))
+        self._untracked.clear()
+
+    def counters(self, tenant: int, rows: int, buckets: int) -> np.ndarray:
+        out = np.empty((rows, buckets), dtype=np.int64)
+        _check(lib().cs_server_read_counters(self._h, tenant, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def stats(self) -> ServerStats:
+        out = ServerStats()
+        _check(lib().cs_server_get_stats(self._h, ctypes.byref(out)))
+        return out
+
+    def replay(self, requests, arrival_s) -> list:
+        """requests: list of (tenant, kind, keys, weights) with device tensors (None for F2);
+        arrival_s: non-decreasing seconds after the call starts.  Returns ServerResult per request."""
+        n = len(requests)
+        reqs = (ServerRequest * n)()
+        for i, (tenant, kind, keys, weights) in enumerate(requests):
+            reqs[i].tenant, reqs[i].kind = tenant, kind
+            if kind == CS_REQ_UPDATE and keys is not None and keys.numel():
+                if _key_dtype(keys) != self._kt or _weight_dtype(weights) != self._wt:
+                    raise ValueError("key or weight dtype differs from the server's")
+                reqs[i].keys, reqs[i].weights, reqs[i].n = keys.data_ptr(), weights.data_ptr(), keys.numel()
+        arr = (ctypes.c_double * n)(*[float(a) for a in arrival_s])
+        res = (ServerResult * n)()
+        _check(lib().cs_server_replay(self._h, reqs, n, arr, res))
+        return list(res)
+
+    def close(self):
+        if self._h:
+            lib().cs_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+            self._untracked.clear()
 
     def __del__(self):
         try:

@@ -36,205 +36,238 @@ struct cs_batch {
   hipGraphExec_t exec = nullptr;
 };
 
+// ---------------------------------------------------------------------------
+// planning (shared with the serving runtime)
+// ---------------------------------------------------------------------------
 namespace {
-
 constexpr uint32_t kDefaultLdsMax = 65536;
 constexpr uint32_t kMaxLdsTable = 160 * 1024;
 constexpr uint32_t kDefaultChunk = 1u << 16;
-constexpr uint64_t kRoundKeys = 1ull << 27;
-
+constexpr uint32_t kGlobalChunk = kBlock * kKeysPerThread;  // one pass of a block: spreads short streams over CUs
+constexpr double kDefaultDirect = 0.125;
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+}  // namespace
 
-void drop_graph(cs_batch* b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
-}
-
-void drop_plan(cs_batch* b) {
-  drop_graph(b);
-  if (b->d_lists) hipFree(b->d_lists);
-  b->d_lists = nullptr;
-  b->lists_bytes = 0;
-  b->rounds.clear();
-  b->planned = false;
-}
-
-// range width of the two-pass update (wave tiles: at most 16 ranges per row)
-bool twopass_shape(const cs_sketch* s, uint32_t* log2g, uint32_t* log2r) {
-  if (s->log2m > 18 || s->rows > 16) return false;
-  uint32_t lr = s->log2m > 3 ? s->log2m - 3 : 0;
-  lr = std::max(lr, kMinRangeLog2);
-  lr = std::min(lr, kMaxRangeLog2);
-  lr = std::min(lr, s->log2m);
+// Range width of the two-pass update in a batch: the widest range pass 2 can
+// hold in LDS (fewest partitions, so the most records per tile and partition);
+// the batch's many segments supply the parallelism.  Wave tiles take at most
+// 16 ranges per row.
+bool mcs::batch_twopass_shape(uint32_t rows, uint32_t log2m, uint32_t* log2g, uint32_t* log2r) {
+  if (log2m > 18 || rows > 16) return false;
+  const uint32_t lr = std::min(log2m, kMaxRangeLog2);
   *log2r = lr;
-  *log2g = s->log2m - lr;
+  *log2g = log2m - lr;
   return (1u << *log2g) <= 16;
 }
 
-cs_status build_plan(cs_batch* b) {
-  drop_plan(b);
-  const DeviceInfo& dev = device_info(b->device);
-  const uint32_t lds_max = b->opts.lds_table_max ? std::min(b->opts.lds_table_max, kMaxLdsTable) : kDefaultLdsMax;
-  const uint64_t chunk = b->opts.lds_chunk_keys ? b->opts.lds_chunk_keys : kDefaultChunk;
-  const bool combine = b->opts.combine >= 0;
-
-  std::vector<BatchSketch> sks;
-  std::vector<BatchLdsItem> lds_items, glb_items;
-  struct Seg { BatchSegment s; uint32_t round; size_t rec_off, desc_off; };
-  std::vector<Seg> segs;
-  std::vector<size_t> round_bytes(1, 0);
+cs_status mcs::batch_plan(const cs_batch_item* items, size_t count, int kb, int wb, const cs_batch_options& opts,
+                          const BatchPlanLimits& lim, BatchPlan* out) {
+  BatchPlan& P = *out;
+  P = BatchPlan{};
+  const uint32_t lds_max = opts.lds_table_max ? std::min(opts.lds_table_max, kMaxLdsTable) : kDefaultLdsMax;
+  const uint64_t chunk = opts.lds_chunk_keys ? opts.lds_chunk_keys : kDefaultChunk;
+  P.combine = opts.combine >= 0;
+  const double direct = opts.direct_fraction == 0.0 ? kDefaultDirect : opts.direct_fraction;
   std::vector<uint64_t> round_keys(1, 0);
-  std::vector<uint32_t> round_tiles(1, 0);
-  uint32_t max_table = 0, max_span = 0, max_wave_lds = 0;
-  b->n_global = b->n_lds = b->n_twopass = 0;
+  std::vector<size_t> round_bytes(1, 0);
+  P.round_tiles.assign(1, 0);
 
-  for (const cs_batch_item& it : b->items) {
+  for (size_t idx = 0; idx < count; ++idx) {
+    const cs_batch_item& it = items[idx];
     if (it.n == 0) continue;
     cs_sketch* s = it.sketch;
     const uint64_t m = 1ull << s->log2m;
     const uint64_t cells = (uint64_t)s->rows << s->log2m;
     BatchSketch bs{it.keys, it.weights, it.n, (const uint4*)s->d_coeffs, (unsigned long long*)s->d_table,
                    s->d_flags, s->rows, s->log2m};
-    if (it.n < m / 8) {  // a table flush would cost more than the direct atomics
-      const uint32_t id = (uint32_t)sks.size();
-      sks.push_back(bs);
-      for (uint64_t o = 0; o < it.n; o += kDefaultChunk)
-        glb_items.push_back(BatchLdsItem{id, 0, o, std::min(it.n, o + kDefaultChunk)});
-      ++b->n_global;
+    if (direct > 0.0 && (double)it.n < direct * (double)m) {  // fewer updates than a flush would touch
+      const uint32_t id = (uint32_t)P.sks.size();
+      P.sks.push_back(bs);
+      for (uint64_t o = 0; o < it.n; o += kGlobalChunk)
+        P.glb_items.push_back(BatchLdsItem{id, 0, o, std::min(it.n, o + kGlobalChunk)});
+      ++P.n_global;
     } else if (cells * 8 <= lds_max) {
-      const uint32_t id = (uint32_t)sks.size();
-      sks.push_back(bs);
+      const uint32_t id = (uint32_t)P.sks.size();
+      P.sks.push_back(bs);
       const uint64_t c = std::max<uint64_t>(chunk, 4 * cells);
-      for (uint64_t o = 0; o < it.n; o += c) lds_items.push_back(BatchLdsItem{id, 0, o, std::min(it.n, o + c)});
-      max_table = std::max<uint32_t>(max_table, (uint32_t)(cells * 8));
-      ++b->n_lds;
+      for (uint64_t o = 0; o < it.n; o += c) P.lds_items.push_back(BatchLdsItem{id, 0, o, std::min(it.n, o + c)});
+      P.max_table = std::max<uint32_t>(P.max_table, (uint32_t)(cells * 8));
+      ++P.n_lds;
     } else {
       uint32_t log2g, log2r;
-      if (!twopass_shape(s, &log2g, &log2r))
+      if (!batch_twopass_shape(s->rows, s->log2m, &log2g, &log2r))
         return fail(CS_EINVAL, "a member's table (rows %u, buckets 2^%u) is too large for the batched update",
                     s->rows, s->log2m);
       const uint32_t G = 1u << log2g;
-      max_span = std::max<uint32_t>(max_span, 1u << log2r);
-      max_wave_lds = std::max<uint32_t>(max_wave_lds, combine ? binw_lds_per_wave<true>(s->rows, G)
-                                                              : binw_lds_per_wave<false>(s->rows, G));
+      P.max_span = std::max<uint32_t>(P.max_span, 1u << log2r);
+      P.max_wave_lds = std::max<uint32_t>(P.max_wave_lds, P.combine ? binw_lds_per_wave<true>(s->rows, G)
+                                                                    : binw_lds_per_wave<false>(s->rows, G));
+      // records and descriptors of one tile (plus up to 512 bytes of alignment per segment)
+      const size_t tile_bytes = (size_t)s->rows * kWaveTile * 4 + (size_t)s->rows * (G + 1) * 4;
+      if (lim.work_cap < tile_bytes + 512)
+        return fail(CS_EINVAL, "workspace of %zu bytes holds no tile of a member with %u rows", lim.work_cap, s->rows);
       uint64_t off = 0;
       while (off < it.n) {
         uint32_t r = (uint32_t)round_keys.size() - 1;
-        if (round_keys[r] >= kRoundKeys) {
+        uint64_t fit_tiles = round_bytes[r] + tile_bytes + 512 <= lim.work_cap
+                                 ? (lim.work_cap - round_bytes[r] - 512) / tile_bytes
+                                 : 0;
+        if (round_keys[r] >= lim.round_keys || fit_tiles == 0) {
           round_keys.push_back(0);
           round_bytes.push_back(0);
-          round_tiles.push_back(0);
+          P.round_tiles.push_back(0);
           ++r;
+          fit_tiles = (lim.work_cap - 512) / tile_bytes;
         }
-        const uint64_t len = std::min(it.n - off, kRoundKeys - round_keys[r]);
+        const uint64_t len = std::min({it.n - off, lim.round_keys - round_keys[r], fit_tiles * kWaveTile});
         const uint32_t tiles = (uint32_t)((len + kWaveTile - 1) / kWaveTile);
-        Seg sg{};
-        sg.s = BatchSegment{(const char*)it.keys + off * b->kb, (const char*)it.weights + off * b->wb, len,
+        BatchPlan::Seg sg{};
+        sg.s = BatchSegment{(const char*)it.keys + off * kb, (const char*)it.weights + off * wb, len,
                             (const uint4*)s->d_coeffs, (unsigned long long*)s->d_table, s->d_flags, nullptr, nullptr,
-                            s->rows, s->log2m, log2g, log2r, round_tiles[r], tiles};
+                            s->rows, s->log2m, log2g, log2r, P.round_tiles[r], tiles};
         sg.round = r;
         sg.rec_off = round_bytes[r];
         round_bytes[r] = align256(round_bytes[r] + (size_t)tiles * s->rows * kWaveTile * 4);
         sg.desc_off = round_bytes[r];
         round_bytes[r] = align256(round_bytes[r] + (size_t)tiles * s->rows * (G + 1) * 4);
         round_keys[r] += len;
-        round_tiles[r] += tiles;
-        segs.push_back(sg);
+        P.round_tiles[r] += tiles;
+        P.segs.push_back(sg);
         off += len;
       }
-      ++b->n_twopass;
+      ++P.n_twopass;
     }
   }
-
-  // workspace: the largest round (rounds run one after another on the stream)
-  size_t work = 0;
-  for (size_t v : round_bytes) work = std::max(work, v);
-  if (work > b->work_bytes) {
-    if (b->d_work) hipFree(b->d_work);
-    b->d_work = nullptr;
-    b->work_bytes = 0;
-    if (hipMalloc(&b->d_work, work) != hipSuccess) return fail(CS_ENOMEM, "batch workspace of %zu bytes", work);
-    b->work_bytes = work;
-  }
-  // segments per round, in round order, with their pass-2 items
-  std::vector<BatchSegment> seg_list;
-  std::vector<BatchAccItem> acc_list;
-  std::vector<uint32_t> seg_first(round_keys.size() + 1, 0), acc_first(round_keys.size() + 1, 0);
-  for (uint32_t r = 0; r < round_keys.size(); ++r) {
-    seg_first[r] = (uint32_t)seg_list.size();
-    acc_first[r] = (uint32_t)acc_list.size();
-    for (const Seg& sg : segs) {
-      if (sg.round != r) continue;
-      BatchSegment x = sg.s;
-      x.recs = (uint32_t*)((char*)b->d_work + sg.rec_off);
-      x.desc = (uint32_t*)((char*)b->d_work + sg.desc_off);
-      const uint32_t local = (uint32_t)(seg_list.size() - seg_first[r]);
-      seg_list.push_back(x);
+  for (size_t v : round_bytes) P.work_bytes = std::max(P.work_bytes, v);
+  // segments are appended round by round, so each round's are contiguous
+  const uint32_t nr = (uint32_t)round_keys.size();
+  P.seg_first.assign(nr + 1, 0);
+  P.acc_first.assign(nr + 1, 0);
+  uint32_t si = 0;
+  for (uint32_t r = 0; r < nr; ++r) {
+    P.seg_first[r] = si;
+    P.acc_first[r] = (uint32_t)P.acc_items.size();
+    for (; si < P.segs.size() && P.segs[si].round == r; ++si) {
+      const BatchSegment& x = P.segs[si].s;
       const uint64_t m = 1ull << x.log2m;
       const uint32_t parts = x.rows << x.log2g;
       const uint32_t slices = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(64, (uint64_t)x.tiles * 128 / m));
+      const uint32_t local = si - P.seg_first[r];
       for (uint32_t pt = 0; pt < parts; ++pt)
-        for (uint32_t sl = 0; sl < slices; ++sl) acc_list.push_back(BatchAccItem{local, pt, sl, slices});
+        for (uint32_t sl = 0; sl < slices; ++sl) P.acc_items.push_back(BatchAccItem{local, pt, sl, slices});
     }
   }
-  seg_first[round_keys.size()] = (uint32_t)seg_list.size();
-  acc_first[round_keys.size()] = (uint32_t)acc_list.size();
+  P.seg_first[nr] = si;
+  P.acc_first[nr] = (uint32_t)P.acc_items.size();
+  P.o_sk = 0;
+  P.o_lds = align256(P.o_sk + P.sks.size() * sizeof(BatchSketch));
+  P.o_glb = align256(P.o_lds + P.lds_items.size() * sizeof(BatchLdsItem));
+  P.o_seg = align256(P.o_glb + P.glb_items.size() * sizeof(BatchLdsItem));
+  P.o_acc = align256(P.o_seg + P.segs.size() * sizeof(BatchSegment));
+  P.lists_bytes = align256(P.o_acc + P.acc_items.size() * sizeof(BatchAccItem)) + 256;
+  return CS_OK;
+}
 
-  // one device allocation for every list
-  const size_t o_sk = 0;
-  const size_t o_lds = align256(o_sk + sks.size() * sizeof(BatchSketch));
-  const size_t o_glb = align256(o_lds + lds_items.size() * sizeof(BatchLdsItem));
-  const size_t o_seg = align256(o_glb + glb_items.size() * sizeof(BatchLdsItem));
-  const size_t o_acc = align256(o_seg + seg_list.size() * sizeof(BatchSegment));
-  const size_t total = align256(o_acc + acc_list.size() * sizeof(BatchAccItem)) + 256;
-  std::vector<char> host(total, 0);
-  memcpy(host.data() + o_sk, sks.data(), sks.size() * sizeof(BatchSketch));
-  memcpy(host.data() + o_lds, lds_items.data(), lds_items.size() * sizeof(BatchLdsItem));
-  memcpy(host.data() + o_glb, glb_items.data(), glb_items.size() * sizeof(BatchLdsItem));
-  memcpy(host.data() + o_seg, seg_list.data(), seg_list.size() * sizeof(BatchSegment));
-  memcpy(host.data() + o_acc, acc_list.data(), acc_list.size() * sizeof(BatchAccItem));
-  if (hipMalloc(&b->d_lists, total) != hipSuccess) return fail(CS_ENOMEM, "batch lists");
-  b->lists_bytes = total;
-  hipError_t e = hipMemcpy(b->d_lists, host.data(), total, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "batch lists upload");
-  char* base = (char*)b->d_lists;
-  for (uint32_t r = 0; r < round_keys.size(); ++r) {
-    if (seg_first[r + 1] == seg_first[r]) continue;
-    BatchRound rd{};
-    rd.segs = (const BatchSegment*)(base + o_seg) + seg_first[r];
-    rd.nsegs = seg_first[r + 1] - seg_first[r];
-    rd.total_tiles = round_tiles[r];
-    rd.acc_items = (const BatchAccItem*)(base + o_acc) + acc_first[r];
-    rd.nacc = acc_first[r + 1] - acc_first[r];
-    b->rounds.push_back(rd);
+void mcs::batch_emit(BatchPlan& P, int prime, int mode, int k, int kb, int wb, const DeviceInfo& dev, char* d_lists,
+                     char* d_work, char* host, BatchLaunch* launch, std::vector<BatchRound>* rounds) {
+  memset(host, 0, P.lists_bytes);
+  memcpy(host + P.o_sk, P.sks.data(), P.sks.size() * sizeof(BatchSketch));
+  memcpy(host + P.o_lds, P.lds_items.data(), P.lds_items.size() * sizeof(BatchLdsItem));
+  memcpy(host + P.o_glb, P.glb_items.data(), P.glb_items.size() * sizeof(BatchLdsItem));
+  BatchSegment* segs = (BatchSegment*)(host + P.o_seg);
+  for (size_t i = 0; i < P.segs.size(); ++i) {
+    segs[i] = P.segs[i].s;
+    segs[i].recs = (uint32_t*)(d_work + P.segs[i].rec_off);
+    segs[i].desc = (uint32_t*)(d_work + P.segs[i].desc_off);
   }
-  BatchLaunch& L = b->launch;
+  memcpy(host + P.o_acc, P.acc_items.data(), P.acc_items.size() * sizeof(BatchAccItem));
+  rounds->clear();
+  for (uint32_t r = 0; r + 1 < P.seg_first.size(); ++r) {
+    if (P.seg_first[r + 1] == P.seg_first[r]) continue;
+    BatchRound rd{};
+    rd.segs = (const BatchSegment*)(d_lists + P.o_seg) + P.seg_first[r];
+    rd.nsegs = P.seg_first[r + 1] - P.seg_first[r];
+    rd.total_tiles = P.round_tiles[r];
+    rd.acc_items = (const BatchAccItem*)(d_lists + P.o_acc) + P.acc_first[r];
+    rd.nacc = P.acc_first[r + 1] - P.acc_first[r];
+    rounds->push_back(rd);
+  }
+  const uint32_t acc_lds = std::max<uint32_t>(P.max_span, 1) * 8;
+  const uint32_t acc_max = dev.cus * std::max<uint32_t>(1, std::min<uint32_t>(2, kMaxLdsTable / acc_lds));
+  for (BatchRound& rd : *rounds) {
+    rd.bin_blocks = std::max<uint32_t>(1, std::min<uint32_t>(dev.cus * 8, (rd.total_tiles + 3) / 4));
+    rd.acc_blocks = std::max<uint32_t>(1, std::min<uint32_t>(acc_max, rd.nacc));
+  }
+  BatchLaunch& L = *launch;
   L = BatchLaunch{};
-  L.prime = b->prime;
-  L.mode = b->mode;
-  L.k = b->k;
-  L.key_bytes = b->kb;
-  L.weight_bytes = b->wb;
-  L.dedup = combine;
-  L.sketches = (const BatchSketch*)(base + o_sk);
-  L.lds_item_list = (const BatchLdsItem*)(base + o_lds);
-  L.lds_items = (uint32_t)lds_items.size();
-  L.lds_bytes = std::max<uint32_t>(max_table, 8);
+  L.prime = prime;
+  L.mode = mode;
+  L.k = k;
+  L.key_bytes = kb;
+  L.weight_bytes = wb;
+  L.dedup = P.combine;
+  L.sketches = (const BatchSketch*)(d_lists + P.o_sk);
+  L.lds_item_list = (const BatchLdsItem*)(d_lists + P.o_lds);
+  L.lds_items = (uint32_t)P.lds_items.size();
+  L.lds_bytes = std::max<uint32_t>(P.max_table, 8);
   const uint32_t lds_per_cu = std::max<uint32_t>(1, std::min<uint32_t>(8, kMaxLdsTable / L.lds_bytes));
   L.lds_blocks = std::max<uint32_t>(1, std::min<uint32_t>(L.lds_items, dev.cus * lds_per_cu));
-  L.glb_item_list = (const BatchLdsItem*)(base + o_glb);
-  L.glb_items = (uint32_t)glb_items.size();
+  L.glb_item_list = (const BatchLdsItem*)(d_lists + P.o_glb);
+  L.glb_items = (uint32_t)P.glb_items.size();
   L.glb_blocks = std::max<uint32_t>(1, std::min<uint32_t>(L.glb_items, dev.cus * 8));
-  L.round_list = b->rounds.data();
-  L.rounds = (uint32_t)b->rounds.size();
-  L.bin_lds_per_wave = std::max<uint32_t>(max_wave_lds, 16);
+  L.round_list = rounds->data();
+  L.rounds = (uint32_t)rounds->size();
+  L.bin_lds_per_wave = std::max<uint32_t>(P.max_wave_lds, 16);
   L.bin_lds_bytes = (kBlock / 64) * L.bin_lds_per_wave;
   L.bin_blocks = dev.cus * 8;
-  L.acc_lds_bytes = std::max<uint32_t>(max_span, 1) * 8;
-  L.acc_blocks = dev.cus * std::max<uint32_t>(1, std::min<uint32_t>(2, kMaxLdsTable / L.acc_lds_bytes));
-  BatchLaunch prep = L;
+  L.acc_lds_bytes = acc_lds;
+  L.acc_blocks = acc_max;
+}
+
+namespace {
+
+void drop_graph(cs_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+void drop_plan(cs_batch* b) {
+  drop_graph(b);
+  if (b->d_lists) (void)hipFree(b->d_lists);
+  b->d_lists = nullptr;
+  b->lists_bytes = 0;
+  b->rounds.clear();
+  b->planned = false;
+}
+
+cs_status build_plan(cs_batch* b) {
+  drop_plan(b);
+  const DeviceInfo& dev = device_info(b->device);
+  BatchPlan P;
+  BatchPlanLimits lim;
+  cs_status st = batch_plan(b->items.data(), b->items.size(), b->kb, b->wb, b->opts, lim, &P);
+  if (st != CS_OK) return st;
+  b->n_global = P.n_global;
+  b->n_lds = P.n_lds;
+  b->n_twopass = P.n_twopass;
+  if (P.work_bytes > b->work_bytes) {
+    if (b->d_work) (void)hipFree(b->d_work);
+    b->d_work = nullptr;
+    b->work_bytes = 0;
+    if (hipMalloc(&b->d_work, P.work_bytes) != hipSuccess)
+      return fail(CS_ENOMEM, "batch workspace of %zu bytes", P.work_bytes);
+    b->work_bytes = P.work_bytes;
+  }
+  if (hipMalloc(&b->d_lists, P.lists_bytes) != hipSuccess) return fail(CS_ENOMEM, "batch lists");
+  b->lists_bytes = P.lists_bytes;
+  std::vector<char> host(P.lists_bytes, 0);
+  batch_emit(P, b->prime, b->mode, b->k, b->kb, b->wb, dev, (char*)b->d_lists, (char*)b->d_work, host.data(),
+             &b->launch, &b->rounds);
+  hipError_t e = hipMemcpy(b->d_lists, host.data(), P.lists_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "batch lists upload");
+  BatchLaunch prep = b->launch;
   prep.prepare_only = true;
   e = launch_batch(prep, 0);
   if (e != hipSuccess) return hip_fail(e, "batch kernel attributes");
@@ -254,7 +287,7 @@ cs_status run_plan(cs_batch* b, hipStream_t stream, bool graph) {
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return hip_fail(e != hipSuccess ? e : e2, "graph capture");
     }
     b->graph = g;
@@ -338,7 +371,8 @@ extern "C" cs_status cs_batch_autotune(cs_batch* b, hipStream_t stream, cs_batch
   std::vector<cs_batch_options> cands;
   for (uint32_t lm : {40960u, 65536u, 163840u})
     for (uint32_t ch : {1u << 15, 1u << 17})
-      for (int cb : {1, -1}) cands.push_back(cs_batch_options{lm, ch, cb, keep.use_graph});
+      for (int cb : {1, -1})
+        for (double df : {1.0 / 128, 0.125, 1.0}) cands.push_back(cs_batch_options{lm, ch, cb, keep.use_graph, df});
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(CS_EDEVICE, "event creation");
@@ -366,8 +400,8 @@ extern "C" cs_status cs_batch_autotune(cs_batch* b, hipStream_t stream, cs_batch
       best_opts = c;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   b->opts = status == CS_OK ? best_opts : keep;
   cs_status st2 = build_plan(b);
   if (status == CS_OK) status = st2;
@@ -382,9 +416,9 @@ extern "C" cs_status cs_batch_autotune(cs_batch* b, hipStream_t stream, cs_batch
 
 extern "C" void cs_batch_destroy(cs_batch* b) {
   if (!b) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   drop_plan(b);
-  if (b->d_work) hipFree(b->d_work);
-  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+  if (b->d_work) (void)hipFree(b->d_work);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   delete b;
 }

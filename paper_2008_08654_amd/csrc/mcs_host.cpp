@@ -136,6 +136,16 @@ static cs_status check_shape(uint32_t rows, uint64_t buckets, cs_prime prime, cs
   return CS_OK;
 }
 
+static uint32_t est_slices_for(uint32_t log2m) {
+  return (uint32_t)std::min<uint64_t>(256, std::max<uint64_t>(1, (1ull << log2m) / 16384));
+}
+
+size_t mcs::sketch_device_bytes(uint32_t rows, uint32_t log2m, cs_mode mode, uint32_t k) {
+  const size_t ncoef = (size_t)rows * npoly(mode) * k;
+  return ((size_t)rows << log2m) * 8 + ncoef * sizeof(uint4) + 64 +
+         sizeof(EstPartial) * rows * est_slices_for(log2m) + sizeof(int64_t) * (rows + 2);
+}
+
 static cs_status create_common(uint32_t rows, uint64_t buckets, cs_prime prime, cs_mode mode, uint32_t k,
                                const std::vector<uint64_t>& coeffs, cs_sketch** out) {
   if (!out) return fail(CS_EINVAL, "out is NULL");
@@ -171,7 +181,7 @@ static cs_status create_common(uint32_t rows, uint64_t buckets, cs_prime prime, 
     cs_destroy(s);
     return fail(CS_ENOMEM, "device allocation of %zu counters: %s", cells, hipGetErrorString(e));
   }
-  s->est_slices = (uint32_t)std::min<uint64_t>(256, std::max<uint64_t>(1, (1ull << l) / 16384));
+  s->est_slices = est_slices_for((uint32_t)l);
   if ((e = hipMalloc(&s->d_est_part, sizeof(EstPartial) * rows * s->est_slices)) != hipSuccess ||
       (e = hipMalloc(&s->d_est_out, sizeof(int64_t) * (rows + 2))) != hipSuccess ||
       (e = hipHostMalloc(&s->h_est_out, sizeof(int64_t) * (rows + 2), hipHostMallocDefault)) != hipSuccess) {
@@ -229,17 +239,17 @@ extern "C" cs_status cs_create_with_coeffs(uint32_t rows, uint64_t buckets, cs_p
 extern "C" void cs_destroy(cs_sketch* s) {
   if (!s) return;
   int cur = -1;
-  hipGetDevice(&cur);
-  if (cur != s->device) hipSetDevice(s->device);
-  hipDeviceSynchronize();
-  if (s->d_table) hipFree(s->d_table);
-  if (s->d_coeffs) hipFree(s->d_coeffs);
-  if (s->d_flags) hipFree(s->d_flags);
-  if (s->d_est_part) hipFree(s->d_est_part);
-  if (s->d_est_out) hipFree(s->d_est_out);
-  if (s->h_est_out) hipHostFree(s->h_est_out);
+  (void)hipGetDevice(&cur);
+  if (cur != s->device) (void)hipSetDevice(s->device);
+  (void)hipDeviceSynchronize();
+  if (s->d_table) (void)hipFree(s->d_table);
+  if (s->d_coeffs) (void)hipFree(s->d_coeffs);
+  if (s->d_flags) (void)hipFree(s->d_flags);
+  if (s->d_est_part) (void)hipFree(s->d_est_part);
+  if (s->d_est_out) (void)hipFree(s->d_est_out);
+  if (s->h_est_out) (void)hipHostFree(s->h_est_out);
   release_workspace(s);
-  if (cur >= 0 && cur != s->device) hipSetDevice(cur);
+  if (cur >= 0 && cur != s->device) (void)hipSetDevice(cur);
   delete s;
 }
 
@@ -405,13 +415,14 @@ extern "C" cs_status cs_set_update_path(cs_sketch* s, int path) {
 // ---------------------------------------------------------------------------
 // estimate, query, reads
 // ---------------------------------------------------------------------------
-static cs_status sticky(const cs_sketch* s, uint32_t flags) {
+cs_status mcs::flags_status(uint32_t flags) {
   if (flags & kFlagDomain)
     return fail(CS_EDOMAIN, "a key was outside the domain (p = 2^61-1 needs keys < 2^60)");
   if (flags & kFlagOverflow) return fail(CS_EOVERFLOW, "an F2 row estimate does not fit in int64");
-  (void)s;
   return CS_OK;
 }
+
+static cs_status sticky(const cs_sketch*, uint32_t flags) { return flags_status(flags); }
 
 extern "C" cs_status cs_estimate_f2(cs_sketch* s, int64_t* f2, int64_t* rows_out, hipStream_t stream) {
   if (!s || !f2) return fail(CS_EINVAL, "sketch or f2 is NULL");
@@ -524,7 +535,7 @@ static uint32_t* divmod_flags() {
     uint32_t* p = nullptr;
     if (hipMalloc(&p, 64) != hipSuccess) return nullptr;
     if (launch_fill_zero((unsigned long long*)p, 8, 0) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-      hipFree(p);
+      (void)hipFree(p);
       return nullptr;
     }
     per_dev[dev] = p;

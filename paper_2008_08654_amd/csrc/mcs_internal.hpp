@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "mcs.h"
+#include "mcs_batch.h"
 #include "sketch_kernels.hpp"
 
 struct cs_sketch {
@@ -48,8 +49,56 @@ cs_status hip_fail(hipError_t e, const char* what);
 UpdatePlan plan_update(const cs_sketch* s, uint64_t n);
 cs_status enqueue_update(cs_sketch* s, const UpdatePlan& plan, const void* keys, int kb, const void* weights, int wb,
                          uint64_t n, hipStream_t stream);
+// Status for device-reported flags (kFlagDomain takes precedence); sets the
+// last-error message.
+cs_status flags_status(uint32_t flags);
+// Device bytes a sketch of this shape holds (table, coefficients, flags,
+// estimate buffers), without the lazily allocated update workspace.
+size_t sketch_device_bytes(uint32_t rows, uint32_t log2m, cs_mode mode, uint32_t k);
+
+// ---------------------------------------------------------------------------
+// Batched-update planning, shared by cs_batch and the serving runtime.
+// batch_plan classifies the members and lays out the two-pass segments in
+// rounds (each round's records and descriptors fit the workspace, rounds run
+// one after another and reuse it); batch_emit then writes the device work
+// lists for a list buffer at a given device address.
+// ---------------------------------------------------------------------------
+struct BatchPlanLimits {
+  uint64_t round_keys = 1ull << 27;  // keys of two-pass segments per round
+  size_t work_cap = ~(size_t)0;      // workspace bytes per round
+};
+
+struct BatchPlan {
+  struct Seg {
+    BatchSegment s;  // recs/desc filled by batch_emit
+    uint32_t round;
+    size_t rec_off, desc_off;
+  };
+  std::vector<BatchSketch> sks;
+  std::vector<BatchLdsItem> lds_items, glb_items;
+  std::vector<Seg> segs;  // in round order
+  std::vector<BatchAccItem> acc_items;
+  std::vector<uint32_t> seg_first, acc_first;  // per round, plus one past the end
+  std::vector<uint32_t> round_tiles;
+  uint32_t max_table = 0, max_span = 0, max_wave_lds = 0;
+  bool combine = true;
+  uint32_t n_global = 0, n_lds = 0, n_twopass = 0;
+  size_t work_bytes = 0;   // workspace the largest round needs
+  size_t lists_bytes = 0;  // bytes of the device work lists
+  size_t o_sk = 0, o_lds = 0, o_glb = 0, o_seg = 0, o_acc = 0;
+};
+
+bool batch_twopass_shape(uint32_t rows, uint32_t log2m, uint32_t* log2g, uint32_t* log2r);
+cs_status batch_plan(const cs_batch_item* items, size_t count, int kb, int wb, const cs_batch_options& opts,
+                     const BatchPlanLimits& lim, BatchPlan* out);
+// Fills host[0, plan.lists_bytes) with the lists as they must appear at device
+// address d_lists, and the launch description (whose pointers refer to
+// d_lists and d_work, except round_list, which points into *rounds).
+void batch_emit(BatchPlan& plan, int prime, int mode, int k, int kb, int wb, const DeviceInfo& dev, char* d_lists,
+                char* d_work, char* host, BatchLaunch* launch, std::vector<BatchRound>* rounds);
+
 inline void release_workspace(cs_sketch* s) {
-  if (s->d_work) hipFree(s->d_work);
+  if (s->d_work) (void)hipFree(s->d_work);
   s->d_work = nullptr;
   s->work_bytes = 0;
 }

@@ -687,46 +687,45 @@ __device__ __forceinline__ void accumulate_item(const AccArgs& args, uint32_t pa
     for (uint32_t i = threadIdx.x; i < span; i += kAccBlock) acc[i] = 0;
     __syncthreads();
     const uint32_t t0 = slice * per, t1 = min(args.tiles, t0 + per);
-    for (uint32_t tb = t0 + wave * 64; tb < t1; tb += nw * 64) {
-      // lane l fetches the group bounds of tile tb + l
+    // each wave takes kU tiles at a time, so every wave of the block shares
+    // even a short slice; lanes 0..kU-1 fetch the tiles' group bounds
+    for (uint32_t tb = t0 + wave * kU; tb < t1; tb += nw * kU) {
       uint32_t lb = 0, le = 0;
-      if (tb + lane < t1) {
+      if (lane < kU && tb + lane < t1) {
         const uint32_t* d = args.desc + ((size_t)(tb + lane) * args.rows + r) * (G + 1) + g;
         lb = d[0];
         le = d[1];
       }
-      const uint32_t ntiles = min(64u, t1 - tb);
-      for (uint32_t u0 = 0; u0 < ntiles; u0 += kU) {
-        uint32_t cur[kU], end[kU];
-        const uint32_t* src[kU];
+      const uint32_t ntiles = min((uint32_t)kU, t1 - tb);
+      uint32_t cur[kU], end[kU];
+      const uint32_t* src[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        cur[u] = __shfl(lb, u, 64);
+        end[u] = (uint32_t)u < ntiles ? __shfl(le, u, 64) : cur[u];
+        src[u] = args.recs + ((size_t)(tb + u) * args.rows + r) * args.tile_keys;
+      }
+      bool more = true;
+      while (more) {
+        uint32_t v[kU];
+        bool has[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-          cur[u] = __shfl(lb, u0 + u, 64);
-          end[u] = u0 + u < ntiles ? __shfl(le, u0 + u, 64) : cur[u];
-          src[u] = args.recs + ((size_t)(tb + u0 + u) * args.rows + r) * args.tile_keys;
+          const uint32_t idx = cur[u] + lane;
+          has[u] = idx < end[u];
+          v[u] = has[u] ? src[u][idx] : 0u;
         }
-        bool more = true;
-        while (more) {
-          uint32_t v[kU];
-          bool has[kU];
 #pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const uint32_t idx = cur[u] + lane;
-            has[u] = idx < end[u];
-            v[u] = has[u] ? src[u][idx] : 0u;
+        for (int u = 0; u < kU; ++u)
+          if (has[u]) {
+            int64_t sw = (int64_t)((int32_t)(v[u] << log2r) >> log2r);
+            atomicAdd(&acc[v[u] >> wbits], (unsigned long long)sw);
           }
+        more = false;
 #pragma unroll
-          for (int u = 0; u < kU; ++u)
-            if (has[u]) {
-              int64_t sw = (int64_t)((int32_t)(v[u] << log2r) >> log2r);
-              atomicAdd(&acc[v[u] >> wbits], (unsigned long long)sw);
-            }
-          more = false;
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            cur[u] += 64;
-            more |= cur[u] < end[u];
-          }
+        for (int u = 0; u < kU; ++u) {
+          cur[u] += 64;
+          more |= cur[u] < end[u];
         }
       }
     }
@@ -784,9 +783,22 @@ __global__ __launch_bounds__(kBlock) void k_query(QueryArgs<KeyT> args) {
 // F2 estimate: per (row, slice) 128-bit partial sums of C^2, then one block
 // adds them, checks the int64 range and takes the median over rows.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_estimate_partial(const int64_t* __restrict__ table, uint32_t log2m,
-                                                             uint32_t slices, EstPartial* __restrict__ part) {
-  const uint32_t row = blockIdx.y, slice = blockIdx.x;
+// A record every lane of the wave reads (a work-list entry), kept in scalar
+// registers.
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T* p) {
+  // all lanes read the same record; copy it through readfirstlane
+  T v = *p;
+  uint32_t* w = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  return v;
+}
+
+// Sum of squares of one slice of one row (128-bit, with a flag once the
+// running sum nears 2^126, far before it could wrap); block-wide.
+__device__ __forceinline__ void est_partial_block(const int64_t* __restrict__ table, uint32_t log2m, uint32_t slices,
+                                                  uint32_t row, uint32_t slice, EstPartial* __restrict__ part) {
   const uint64_t m = 1ull << log2m;
   const uint64_t per = (m + slices - 1) / slices;
   const uint64_t b = (uint64_t)slice * per, e = min(m, b + per);
@@ -798,7 +810,7 @@ __global__ __launch_bounds__(kBlock) void k_estimate_partial(const int64_t* __re
     uint64_t mag = c < 0 ? 0ull - (uint64_t)c : (uint64_t)c;
     unsigned __int128 sq = (unsigned __int128)mag * mag;
     acc += sq;
-    big |= (uint32_t)(acc >> 126);  // keeps the running sum far from wrapping
+    big |= (uint32_t)(acc >> 126);
   }
   __shared__ unsigned long long s_lo[kBlock], s_hi[kBlock];
   __shared__ uint32_t s_big;
@@ -824,11 +836,14 @@ __global__ __launch_bounds__(kBlock) void k_estimate_partial(const int64_t* __re
     o.hi = s_hi[0];
     o.big = s_big;
   }
+  __syncthreads();  // the shared arrays are reused by the block's next item
 }
 
-__global__ void k_estimate_final(const EstPartial* __restrict__ part, uint32_t rows, uint32_t slices,
-                                 int64_t* __restrict__ out, uint32_t* flags) {
-  // out[0] = median, out[1..rows] = X_j ; one thread per row, then thread 0 sorts
+// Row totals X_j, their median (element (rows-1)/2 of the sorted values) and
+// the flags word: out[0] = median, out[1..rows] = X_j, out[1+rows] = flags.
+// Block-wide.
+__device__ __forceinline__ void est_final_block(const EstPartial* __restrict__ part, uint32_t rows, uint32_t slices,
+                                                int64_t* __restrict__ out, const uint32_t* flags) {
   __shared__ int64_t vals[kMaxRows];
   __shared__ uint32_t over;
   if (threadIdx.x == 0) over = 0;
@@ -864,7 +879,43 @@ __global__ void k_estimate_final(const EstPartial* __restrict__ part, uint32_t r
     }
     out[0] = vals[(rows - 1) / 2];
     // overflow concerns this estimate only; the sticky flags are reported alongside
-    out[1 + rows] = (int64_t)((*(volatile uint32_t*)flags) | (over ? kFlagOverflow : 0u));
+    out[1 + rows] = (int64_t)((*(volatile const uint32_t*)flags) | (over ? kFlagOverflow : 0u));
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void k_estimate_partial(const int64_t* __restrict__ table, uint32_t log2m,
+                                                             uint32_t slices, EstPartial* __restrict__ part) {
+  est_partial_block(table, log2m, slices, blockIdx.y, blockIdx.x, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_estimate_final(const EstPartial* __restrict__ part, uint32_t rows,
+                                                           uint32_t slices, int64_t* __restrict__ out,
+                                                           uint32_t* flags) {
+  est_final_block(part, rows, slices, out, flags);
+}
+
+// Estimates of many sketches in two launches: blocks [first, first + rows *
+// slices) of the partial kernel belong to item i; one final block per item.
+__global__ __launch_bounds__(kBlock) void k_batch_est_partial(const BatchEstItem* __restrict__ items, uint32_t nitems,
+                                                              uint32_t total_blocks) {
+  for (uint32_t b = blockIdx.x; b < total_blocks; b += gridDim.x) {
+    uint32_t lo = 0, hi = nitems;  // last item with first <= b
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (uniform_load(&items[mid].first_block) <= b) lo = mid; else hi = mid;
+    }
+    const BatchEstItem it = uniform_load(items + lo);
+    const uint32_t local = b - it.first_block;
+    est_partial_block(it.table, it.log2m, it.slices, local / it.slices, local % it.slices, it.part);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_est_final(const BatchEstItem* __restrict__ items, uint32_t nitems,
+                                                            int64_t* __restrict__ out) {
+  for (uint32_t i = blockIdx.x; i < nitems; i += gridDim.x) {
+    const BatchEstItem it = uniform_load(items + i);
+    est_final_block(it.part, it.rows, it.slices, out + it.out_offset, it.flags);
   }
 }
 
@@ -887,16 +938,6 @@ __global__ void k_fill_zero(unsigned long long* __restrict__ dst, uint64_t n) {
 //                 a wave finds its segment by binary search on tile_begin
 //   k_batch_acc:  pass 2 items (segment, partition, slice)
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T uniform_load(const T* p) {
-  // all lanes read the same record; copy it through readfirstlane
-  T v = *p;
-  uint32_t* w = reinterpret_cast<uint32_t*>(&v);
-#pragma unroll
-  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
-  return v;
-}
-
 template <int PRIME, int MODE, int K, typename KeyT, typename WT>
 __global__ __launch_bounds__(kBlock) void k_batch_lds(const BatchSketch* __restrict__ sks,
                                                       const BatchLdsItem* __restrict__ items, uint32_t nitems) {
@@ -980,14 +1021,14 @@ static hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t st) {
   for (uint32_t r = 0; r < b.rounds; ++r) {
     const BatchRound& rd = b.round_list[r];
     if (b.dedup)
-      hipLaunchKernelGGL((k_batch_bin<PRIME, MODE, K, KeyT, WT, true>), dim3(b.bin_blocks), dim3(kBlock),
+      hipLaunchKernelGGL((k_batch_bin<PRIME, MODE, K, KeyT, WT, true>), dim3(rd.bin_blocks), dim3(kBlock),
                          b.bin_lds_bytes, st, rd.segs, rd.nsegs, rd.total_tiles, b.bin_lds_per_wave);
     else
-      hipLaunchKernelGGL((k_batch_bin<PRIME, MODE, K, KeyT, WT, false>), dim3(b.bin_blocks), dim3(kBlock),
+      hipLaunchKernelGGL((k_batch_bin<PRIME, MODE, K, KeyT, WT, false>), dim3(rd.bin_blocks), dim3(kBlock),
                          b.bin_lds_bytes, st, rd.segs, rd.nsegs, rd.total_tiles, b.bin_lds_per_wave);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch_acc, dim3(b.acc_blocks), dim3(kAccBlock), b.acc_lds_bytes, st, rd.segs, rd.acc_items,
+    hipLaunchKernelGGL(k_batch_acc, dim3(rd.acc_blocks), dim3(kAccBlock), b.acc_lds_bytes, st, rd.segs, rd.acc_items,
                        rd.nacc);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1132,6 +1173,16 @@ hipError_t launch_estimate(const int64_t* table, uint32_t rows, uint32_t log2m, 
                            int64_t* out, uint32_t* flags, hipStream_t st) {
   hipLaunchKernelGGL(k_estimate_partial, dim3(slices, rows), dim3(kBlock), 0, st, table, log2m, slices, part);
   hipLaunchKernelGGL(k_estimate_final, dim3(1), dim3(kBlock), 0, st, part, rows, slices, out, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_estimate(const BatchEstItem* items, uint32_t nitems, uint32_t total_blocks, int64_t* out,
+                                 uint32_t cus, hipStream_t st) {
+  if (nitems == 0) return hipSuccess;
+  const uint32_t pb = std::max<uint32_t>(1, std::min<uint32_t>(total_blocks, cus * 8));
+  hipLaunchKernelGGL(k_batch_est_partial, dim3(pb), dim3(kBlock), 0, st, items, nitems, total_blocks);
+  const uint32_t fb = std::max<uint32_t>(1, std::min<uint32_t>(nitems, cus * 8));
+  hipLaunchKernelGGL(k_batch_est_final, dim3(fb), dim3(kBlock), 0, st, items, nitems, out);
   return hipGetLastError();
 }
 

@@ -152,6 +152,18 @@ struct EstPartial {
 
 hipError_t launch_update(const UpdatePlan& plan, const UpdateArgsAny& a, hipStream_t st);
 
+// one F2 estimate of a batch: partial-kernel blocks [first_block, first_block +
+// rows * slices), results (median, rows values, flags) at out[out_offset...]
+struct BatchEstItem {
+  const int64_t* table;
+  EstPartial* part;  // rows * slices partial sums (the sketch's own buffer)
+  const uint32_t* flags;
+  uint32_t rows, log2m, slices, first_block;
+  uint64_t out_offset;
+};
+hipError_t launch_batch_estimate(const BatchEstItem* items, uint32_t nitems, uint32_t total_blocks, int64_t* out,
+                                 uint32_t cus, hipStream_t st);
+
 // ---------------------------------------------------------------------------
 // batched update
 // ---------------------------------------------------------------------------
@@ -183,12 +195,13 @@ struct BatchSegment {         // keys of one two-pass sketch handled in a round
 struct BatchAccItem {
   uint32_t segment, part, slice, slices;
 };
-struct BatchRound {
+struct BatchRound {           // host-side description of one pass-1/pass-2 round
   const BatchSegment* segs;
   uint32_t nsegs;
   uint32_t total_tiles;
   const BatchAccItem* acc_items;
   uint32_t nacc;
+  uint32_t bin_blocks, acc_blocks;  // grids of the round (grid-stride kernels)
 };
 struct BatchLaunch {
   int prime, mode, k, key_bytes, weight_bytes;

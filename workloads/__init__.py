@@ -216,6 +216,27 @@ def stream_uniform_u64(n: int = 1 << 26, device="cpu", seed: int = DATA_SEED + 2
     return keys, w
 
 
+def served_tenants(count: int = 1024, seed: int = DATA_SEED + 5):
+    """Served workload tenants: log2 of the bucket count uniform in {12..18} (7 rows each)."""
+    return bounded_int(seed, count, 12, 18, stream=6)
+
+
+def served_requests(n: int, tenants: int, seed: int = DATA_SEED + 5, f2_frac: float = 0.1):
+    """Served workload requests: tenant uniform, F2 query with probability f2_frac, otherwise an
+    update of floor(2^U(10, 20)) keys.  Returns (tenant, is_f2, size) CPU int64 tensors (size 0
+    for F2)."""
+    tenant = bounded_int(seed, n, 0, tenants - 1, stream=7)
+    is_f2 = (uniform01(seed, 8, _arange(n, "cpu")) < f2_frac).to(torch.int64)
+    size = loguniform_int(seed, n, 10.0, 20.0, stream=9) * (1 - is_f2)
+    return tenant, is_f2, size
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = DATA_SEED + 5, stream: int = 10):
+    """Arrival times (seconds, float64, CPU) of a Poisson process of the given rate."""
+    u = uniform01(seed, stream, _arange(n, "cpu"))
+    return torch.cumsum(-torch.log1p(-u) / rate, 0)
+
+
 def log2_ceil(v: int) -> int:
     return max(0, (v - 1).bit_length())
 
