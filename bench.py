@@ -67,6 +67,44 @@ DIVMOD_WORKLOADS = {
 }
 
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic.json")
+# The measured HBM traffic stands only for the kernels it was measured on.
+KERNEL_SOURCES = ["paper_2008_08654_amd/csrc/" + f for f in
+                  ("sketch_kernels.hip", "sketch_kernels.hpp", "field.hpp", "divmod_kernels.hip", "mcs_host.cpp")]
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs (copy-calibrated),
+    or None when there is no measurement or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = t.get("workloads", {}).get(workload)
+    if entry is None or t.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+def update_kernels(sk, n) -> str:
+    """The dispatches one cs_update of n keys makes (to match against a kernel profile)."""
+    chunks = -(-n // (1 << 27))
+    if sk.rows * sk.buckets * 8 <= 65536:
+        return "1 x k_update_lds"
+    return f"{chunks} x (k_bin_wave or k_bin) + {chunks} x k_accumulate (chunks of 2^27 keys)"
+
+
 def _stream_ptr(torch):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -171,8 +209,11 @@ def run_sketch(args, wl):
                       "update_only_gkeys_per_s": round(n / (upd_avg_ms * 1e-3) / 1e9, 3),
                       "input_generation_s": round(t_gen, 2)},
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                        "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                        "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                        "traffic": measured_traffic(args.workload),
+                        "algorithmic_bytes_per_launch": bytes_key * n,
                         "kernel": "cs_update", "kernel_avg_ms": round(upd_avg_ms, 4),
+                        "kernels_per_launch": update_kernels(sk, n),
                         "algorithmic_ops_per_key": ops_key,
                         "hbm_frac_of_input_stream": round(bytes_key * n / (upd_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
     if not args.no_cpu_baseline:
@@ -431,7 +472,8 @@ def run_divmod(args, wl):
                       "naive_kernel_ms_scaled": None if naive_ms is None else round(naive_ms, 3),
                       "speedup_vs_naive": None if naive_ms is None else round(naive_ms / k_ms, 2)},
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_divmod",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
+                        "algorithmic_bytes_per_launch": bytes_per * n, "kernel": "k_divmod",
                         "kernel_avg_ms": round(k_ms, 4), "algorithmic_bytes_per_value": bytes_per}}
     if not args.no_cpu_baseline:
         import oracle as O
@@ -456,6 +498,8 @@ def main():
     ap.add_argument("--path", type=int, default=0, help="force an update path (1 LDS, 2 global, 3 binned)")
     ap.add_argument("--direct-fraction", type=float, default=0.0,
                     help="served: updates with n < f * buckets use direct atomics (0: library default)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy 1 GiB device to device (reference dispatch for HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-naive", action="store_true")
     args = ap.parse_args()
@@ -463,6 +507,13 @@ def main():
         print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one GPU "
               f"(the sketch shards by key range plus one int64 all-reduce, not built here)", file=sys.stderr)
         sys.exit(2)
+    if args.calib_copy:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "batched":
         out = run_batched(args)
     elif args.workload == "served":
