@@ -56,6 +56,9 @@ SKETCH_WORKLOADS = {
     "small_table_u32": dict(n=1 << 28, rows=5, log2m=10, mode=0, prime="p61", keys="u32", kbytes=4, wbytes=8,
                             seed=1001, desc="2^28 uint32 keys uniform, int64 weights = 1, p=2^61-1, t=5, m=2^10 "
                                             "(table in LDS), two-for-one"),
+    "small_table_u32_two_poly": dict(n=1 << 28, rows=5, log2m=10, mode=2, prime="p61", keys="u32", kbytes=4,
+                                     wbytes=8, seed=1001, desc="as small_table_u32 with two independent polynomials "
+                                                               "per row (bucket, sign): the hashing-bound comparison"),
     "p89_uniform": dict(n=1 << 26, rows=5, log2m=20, mode=0, prime="p89", keys="u64", kbytes=8, wbytes=8,
                         seed=1003, desc="2^26 uint64 keys uniform, int64 weights = 1, p=2^89-1, t=5, m=2^20, "
                                         "two-for-one"),
@@ -83,16 +86,17 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, n: int):
     """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs (copy-calibrated),
-    or None when there is no measurement or the kernel sources changed since it was taken."""
+    or None when there is no measurement for this workload and size, or the kernel sources
+    changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     entry = t.get("workloads", {}).get(workload)
-    if entry is None or t.get("sources_sha256") != kernel_sources_sha256():
+    if entry is None or entry.get("n") != n or t.get("sources_sha256") != kernel_sources_sha256():
         return None
     return entry.get("hbm_bytes_per_launch")
 
@@ -210,7 +214,7 @@ def run_sketch(args, wl):
                       "input_generation_s": round(t_gen, 2)},
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                         "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                        "traffic": measured_traffic(args.workload),
+                        "traffic": measured_traffic(args.workload, n),
                         "algorithmic_bytes_per_launch": bytes_key * n,
                         "kernel": "cs_update", "kernel_avg_ms": round(upd_avg_ms, 4),
                         "kernels_per_launch": update_kernels(sk, n),
@@ -472,7 +476,7 @@ def run_divmod(args, wl):
                       "naive_kernel_ms_scaled": None if naive_ms is None else round(naive_ms, 3),
                       "speedup_vs_naive": None if naive_ms is None else round(naive_ms / k_ms, 2)},
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload),
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, n),
                         "algorithmic_bytes_per_launch": bytes_per * n, "kernel": "k_divmod",
                         "kernel_avg_ms": round(k_ms, 4), "algorithmic_bytes_per_value": bytes_per}}
     if not args.no_cpu_baseline:
