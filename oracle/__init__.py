@@ -33,7 +33,7 @@ P89 = (1 << 89) - 1
 P64_59 = (1 << 64) - 59
 
 PRIME_P61, PRIME_P89, PRIME_P64_59 = 1, 2, 3
-TWO_FOR_ONE, TWO_FOR_ONE_MSB, TWO_POLY = 0, 1, 2
+TWO_FOR_ONE, TWO_FOR_ONE_MSB, TWO_POLY, ARB_R = 0, 1, 2, 3
 
 OK, EINVAL, EDOMAIN, EOVERFLOW = 0, -1, -3, -4
 
@@ -80,10 +80,12 @@ def _load():
             lib.orc_enum_hash.argtypes = [u64, u32, P, u32, P]
             lib.orc_enum_bucket_sign.argtypes = [u64, u32, u32, i32, u64, P, u32, P, P]
             lib.orc_enum_estimate_moments.argtypes = [u64, u32, u32, i32, u64, P, P, u64, P, P]
+            lib.orc_bucket_map_exact.argtypes = [u64, u64, P, u64, u64, P]
+            lib.orc_bucket_map_mersenne.argtypes = [u32, P, u64, u64, P]
             for f in (lib.orc_cs_update_small, lib.orc_cs_update_small_keypar, lib.orc_cs_update_p89,
                       lib.orc_bucket_sign_small, lib.orc_bucket_sign_p89, lib.orc_cs_estimate,
                       lib.orc_exact_f2, lib.orc_divmod, lib.orc_enum_hash, lib.orc_enum_bucket_sign,
-                      lib.orc_enum_estimate_moments):
+                      lib.orc_enum_estimate_moments, lib.orc_bucket_map_exact, lib.orc_bucket_map_mersenne):
                 f.restype = i32
             _lib = lib
     return _lib
@@ -255,6 +257,41 @@ def divmod_batch(prime: int, x: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
     if w == 1:
         return q.reshape(-1), r.reshape(-1)
     return q, r
+
+
+# --------------------------------------------------------------------------
+# maps of hash values in [p] to [r] buckets (Sections 1.4 and 1.5)
+# --------------------------------------------------------------------------
+def _limbs2(v) -> np.ndarray:
+    """Values below 2^128 (Python ints or a uint64 array) as an (n, 2) uint64 limb array."""
+    a = np.asarray(v)
+    if a.ndim == 2:
+        return np.ascontiguousarray(a.astype(np.uint64))
+    if a.dtype == np.uint64 or (a.dtype.kind in "iu" and a.dtype.itemsize <= 8):
+        out = np.zeros((a.shape[0], 2), dtype=np.uint64)
+        out[:, 0] = _u64(a)
+        return out
+    out = np.zeros((len(v), 2), dtype=np.uint64)
+    for i, x in enumerate(v):
+        out[i, 0], out[i, 1] = int(x) & 0xFFFFFFFFFFFFFFFF, int(x) >> 64
+    return out
+
+
+def bucket_map_exact(p: int, v, r: int) -> np.ndarray:
+    """floor(v * r / p) for each v in [p] (p < 2^89), as uint32."""
+    x = _limbs2(v)
+    out = np.zeros(x.shape[0], dtype=np.uint32)
+    _check(_load().orc_bucket_map_exact(p & 0xFFFFFFFFFFFFFFFF, p >> 64, _ptr(x), x.shape[0], r, _ptr(out)),
+           "bucket_map_exact")
+    return out
+
+
+def bucket_map_mersenne(b: int, v, r: int) -> np.ndarray:
+    """floor((v + 1) * r / 2^b) for each v in [2^b - 1], as uint32."""
+    x = _limbs2(v)
+    out = np.zeros(x.shape[0], dtype=np.uint32)
+    _check(_load().orc_bucket_map_mersenne(b, _ptr(x), x.shape[0], r, _ptr(out)), "bucket_map_mersenne")
+    return out
 
 
 # --------------------------------------------------------------------------

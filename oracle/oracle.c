@@ -33,7 +33,7 @@ typedef __int128 i128;
 #define ORC_EDOMAIN (-3)
 #define ORC_EOVERFLOW (-4)
 
-enum { ORC_TWO_FOR_ONE = 0, ORC_TWO_FOR_ONE_MSB = 1, ORC_TWO_POLY = 2 };
+enum { ORC_TWO_FOR_ONE = 0, ORC_TWO_FOR_ONE_MSB = 1, ORC_TWO_POLY = 2, ORC_ARB_R = 3 };
 
 /* ------------------------------------------------------------------------ */
 /* Seed expansion: SplitMix64 (Steele, Lea and Flood, OOPSLA 2014), the     */
@@ -165,12 +165,26 @@ static void split(int mode, uint64_t m, uint64_t h1_lo, uint32_t h1_top, uint64_
   *sign = 1 - 2 * (int)a;
 }
 
+/* ARB_R, any number r of buckets (Algorithm 8, Section 3.3): with
+ * h_x = h(x) + 1 (a b-bit value, never 0), the bucket is
+ * floor(r * j / 2^(b-1)) for j = the low b-1 bits of h_x, and the sign bit
+ * is bit b-1 of h_x; s = 1 - 2a as the algorithm writes it.  Plain 128-bit
+ * arithmetic: h < 2^89 and r < 2^32, so r * j < 2^120. */
+static void split_arb(uint32_t b, uint64_t r, u128 h, uint64_t* bucket, int* sign) {
+  const u128 hx = h + 1;
+  const u128 j = hx & ((((u128)1) << (b - 1)) - 1);
+  const uint32_t a = (uint32_t)(hx >> (b - 1)) & 1;
+  *bucket = (uint64_t)(((u128)r * j) >> (b - 1));
+  *sign = 1 - 2 * (int)a;
+}
+
 static int npoly(int mode) { return mode == ORC_TWO_POLY ? 2 : 1; }
 
 /* m must be a power of two 2^l, with l <= b-1 when one hash value supplies
  * both the bucket and the sign bit (the bits must be distinct), l <= b
- * otherwise. */
+ * otherwise.  ARB_R takes any 2 <= m <= 2^(b-1) below 2^32. */
 static int check_m(uint64_t m, uint32_t b, int mode) {
+  if (mode == ORC_ARB_R) return m >= 2 && m < (1ULL << 32) && (b > 33 || m <= (1ULL << (b - 1)));
   if (m == 0 || (m & (m - 1)) != 0) return 0;
   uint32_t l = 0;
   while ((1ULL << l) < m) ++l;
@@ -184,6 +198,10 @@ int orc_bucket_sign_small(uint64_t p, uint32_t b, uint32_t k, int mode, uint64_t
                           uint64_t* bucket, int* sign) {
   const uint64_t* a = coeffs + (uint64_t)row * npoly(mode) * k;
   uint64_t h1 = orc_hash_small(p, a, k, x);
+  if (mode == ORC_ARB_R) {
+    split_arb(b, m, h1, bucket, sign);
+    return ORC_OK;
+  }
   uint64_t h2 = mode == ORC_TWO_POLY ? orc_hash_small(p, a + k, k, x) : 0;
   split(mode, m, h1, (uint32_t)((h1 >> (b - 1)) & 1), h2, bucket, sign);
   return ORC_OK;
@@ -194,6 +212,10 @@ int orc_bucket_sign_p89(uint32_t k, int mode, uint64_t m, const uint64_t* coeffs
   const uint64_t* a = coeffs + (uint64_t)row * npoly(mode) * k * 2;
   uint64_t h1[2], h2[2] = {0, 0};
   orc_hash_p89(a, k, x, h1);
+  if (mode == ORC_ARB_R) {
+    split_arb(89, m, ((u128)h1[1] << 64) | h1[0], bucket, sign);
+    return ORC_OK;
+  }
   if (mode == ORC_TWO_POLY) orc_hash_p89(a + 2 * k, k, x, h2);
   split(mode, m, h1[0], (uint32_t)((h1[1] >> (88 - 64)) & 1), h2[0], bucket, sign);
   return ORC_OK;
@@ -210,7 +232,7 @@ int orc_bucket_sign_p89(uint32_t k, int mode, uint64_t m, const uint64_t* coeffs
 int orc_cs_update_small(uint64_t p, uint32_t b, uint32_t k, int mode, uint32_t rows, uint64_t m,
                         const uint64_t* coeffs, const uint64_t* keys, const int64_t* weights,
                         uint64_t n, int64_t* table) {
-  if (rows == 0 || k == 0 || mode < 0 || mode > 2 || !check_m(m, b, mode)) return ORC_EINVAL;
+  if (rows == 0 || k == 0 || mode < 0 || mode > 3 || !check_m(m, b, mode)) return ORC_EINVAL;
   if (p == (1ULL << 61) - 1) {
     for (uint64_t i = 0; i < n; ++i)
       if (keys[i] >= (1ULL << 60)) return ORC_EDOMAIN;
@@ -229,7 +251,7 @@ int orc_cs_update_small(uint64_t p, uint32_t b, uint32_t k, int mode, uint32_t r
 
 int orc_cs_update_p89(uint32_t k, int mode, uint32_t rows, uint64_t m, const uint64_t* coeffs,
                       const uint64_t* keys, const int64_t* weights, uint64_t n, int64_t* table) {
-  if (rows == 0 || k == 0 || mode < 0 || mode > 2 || !check_m(m, 89, mode)) return ORC_EINVAL;
+  if (rows == 0 || k == 0 || mode < 0 || mode > 3 || !check_m(m, 89, mode)) return ORC_EINVAL;
 #pragma omp parallel for schedule(dynamic, 1) if (rows > 1)
   for (uint32_t j = 0; j < rows; ++j) {
     uint64_t* row = (uint64_t*)table + (uint64_t)j * m;
@@ -249,7 +271,7 @@ int orc_cs_update_p89(uint32_t k, int mode, uint32_t rows, uint64_t m, const uin
 int orc_cs_update_small_keypar(uint64_t p, uint32_t b, uint32_t k, int mode, uint32_t rows,
                                uint64_t m, const uint64_t* coeffs, const uint64_t* keys,
                                const int64_t* weights, uint64_t n, int64_t* table, int nthreads) {
-  if (rows == 0 || k == 0 || nthreads < 1 || mode < 0 || mode > 2 || !check_m(m, b, mode))
+  if (rows == 0 || k == 0 || nthreads < 1 || mode < 0 || mode > 3 || !check_m(m, b, mode))
     return ORC_EINVAL;
   if (p == (1ULL << 61) - 1) {
     for (uint64_t i = 0; i < n; ++i)
@@ -374,6 +396,36 @@ int orc_divmod(int prime, const uint64_t* x, uint64_t n, uint64_t* quot, uint64_
 }
 
 /* ------------------------------------------------------------------------ */
+/* Maps of a hash value v in [p] to [r] buckets (Section 1.4 and the note on */
+/* arbitrary bucket counts in Section 1.5), as plain definitions:           */
+/*   exact:    floor(v * r / p)           (most uniform for any p)          */
+/*   mersenne: floor((v + 1) * r / 2^b)   (eq. most-uniform, p = 2^b - 1)   */
+/* v is given as two little-endian limbs, v < p < 2^89, r < 2^32.  A value  */
+/* v >= p returns ORC_EDOMAIN.                                               */
+/* ------------------------------------------------------------------------ */
+int orc_bucket_map_exact(uint64_t p_lo, uint64_t p_hi, const uint64_t* v, uint64_t n, uint64_t r, uint32_t* out) {
+  const u128 p = ((u128)p_hi << 64) | p_lo;
+  if (r == 0 || r >= (1ULL << 32) || p < 2 || p_hi >= (1ULL << 25)) return ORC_EINVAL;
+  for (uint64_t i = 0; i < n; ++i) {
+    const u128 x = ((u128)v[2 * i + 1] << 64) | v[2 * i];
+    if (x >= p) return ORC_EDOMAIN;
+    out[i] = (uint32_t)((x * r) / p);
+  }
+  return ORC_OK;
+}
+
+int orc_bucket_map_mersenne(uint32_t b, const uint64_t* v, uint64_t n, uint64_t r, uint32_t* out) {
+  if (r == 0 || r >= (1ULL << 32) || b < 2 || b > 89) return ORC_EINVAL;
+  const u128 p = (((u128)1) << b) - 1;
+  for (uint64_t i = 0; i < n; ++i) {
+    const u128 x = ((u128)v[2 * i + 1] << 64) | v[2 * i];
+    if (x >= p) return ORC_EDOMAIN;
+    out[i] = (uint32_t)(((x + 1) * r) >> b);
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Exhaustive enumeration over every coefficient vector a in Z_p^k, for     */
 /* the tiny-prime checks of the oracle against the paper's exact            */
 /* statements.  Tuple index t = a_0 + p a_1 + p^2 a_2 + ... (a_0 fastest).  */
@@ -427,7 +479,7 @@ int orc_enum_estimate_moments(uint64_t p, uint32_t b, uint32_t k, int mode, uint
                               uint64_t sum_x[2], uint64_t sum_x2[2]) {
   uint64_t a[32] = {0};
   uint32_t ncoef = (uint32_t)npoly(mode) * k;
-  if (k == 0 || ncoef > 32 || mode < 0 || mode > 2 || !check_m(m, b, mode)) return ORC_EINVAL;
+  if (k == 0 || ncoef > 32 || mode < 0 || mode > 3 || !check_m(m, b, mode)) return ORC_EINVAL;
   int64_t* table = (int64_t*)malloc(sizeof(int64_t) * m);
   u128 s1 = 0, s2 = 0;
   do {

@@ -442,3 +442,154 @@ def test_oracle_is_independent_of_the_library():
             with open(os.path.join(here, name)) as f:
                 src = f.read()
             assert "paper_2008_08654_amd" not in src and "libmcs" not in src and "mcs.h" not in src, name
+
+
+# ---------------------------------------------------------------------------
+# arbitrary numbers of buckets: most uniform maps (Section 1.4, Lemma
+# most-uniform; Section 1.5 on pseudo-Mersenne primes) and Algorithm 8
+# (Section 3.3, eq. prix0 / prixneq0, Lemma ix-r-dist, Lemma
+# remove-si-r-dist, Theorem h-and-s-p-arb-r)
+# ---------------------------------------------------------------------------
+def _most_uniform(counts, q, r):
+    lo, hi = q // r, -(-q // r)
+    return len(counts) == r and all(c in (lo, hi) for c in counts) and sum(counts) == q
+
+
+@pytest.mark.parametrize("b", [5, 7, 13])
+@pytest.mark.parametrize("r", [2, 3, 5, 6, 7, 10, 12, 16, 31])
+def test_mersenne_map_is_most_uniform(b, r):
+    """Lemma most-uniform (iii): v -> ((v+1) r) >> b is most uniform from [2^b - 1] to [r]."""
+    if r > (1 << b) - 1:
+        pytest.skip("more buckets than values")
+    q = (1 << b) - 1
+    out = O.bucket_map_mersenne(b, list(range(q)), r)
+    assert _most_uniform(np.bincount(out, minlength=r).tolist(), q, r)
+    assert (np.diff(out.astype(np.int64)) >= 0).all()
+
+
+def test_plus_c_trick_fails_for_pseudo_mersenne():
+    """Section 1.4: for q = 2^b - c with c >= 2, v -> ((v+c) r) >> b leaves bucket 0 with
+    ceil(2^b / r) - c values, so it is not most uniform in general (negative control on
+    the counting used by the pins above)."""
+    b, c, r = 8, 5, 7           # q = 251
+    q = (1 << b) - c
+    counts = np.bincount([((v + c) * r) >> b for v in range(q)], minlength=r).tolist()
+    assert counts[0] == -(-(1 << b) // r) - c
+    assert not _most_uniform(counts, q, r)
+
+
+@pytest.mark.parametrize("p", [31, 127, 251, 8191, 65521])
+@pytest.mark.parametrize("r", [2, 3, 7, 10, 30])
+def test_exact_map_is_most_uniform(p, r):
+    """floor(v r / p) is most uniform from [p] to [r] for any p (Section 1.4), including the
+    pseudo-Mersenne 251 = 2^8 - 5 and 65521 = 2^16 - 15 (Section 1.5)."""
+    out = O.bucket_map_exact(p, list(range(p)), r)
+    assert _most_uniform(np.bincount(out, minlength=r).tolist(), p, r)
+    assert (np.diff(out.astype(np.int64)) >= 0).all()
+
+
+def test_maps_at_the_large_primes_edges():
+    """Edges of the three library primes: v = 0 lands in bucket 0 and v = p - 1 in bucket
+    r - 1; v >= p is outside the domain."""
+    for p, b in (((1 << 61) - 1, 61), ((1 << 89) - 1, 89), ((1 << 64) - 59, None)):
+        for r in (1, 2, 1000, (1 << 32) - 1):
+            e = O.bucket_map_exact(p, [0, p - 1], r)
+            assert e.tolist() == [0, r - 1]
+            if b is not None:
+                f = O.bucket_map_mersenne(b, [0, p - 1], r)
+                assert f.tolist() == [r >> b, r - 1]
+        with pytest.raises(O.OracleError):
+            O.bucket_map_exact(p, [p], 10)
+
+
+def _arb_split_all_h(p, b, r):
+    """(bucket, sign) of Algorithm 8 for every hash value h in [p]: with k = 1 the
+    polynomial is the constant a_0, so enumerating a_0 enumerates h."""
+    bk, sg = O.enum_bucket_sign(p, b, 1, O.ARB_R, r, [3])
+    return bk[:, 0].astype(np.int64), sg[:, 0].astype(np.int64)
+
+
+@pytest.mark.parametrize("p,b", [(31, 5), (127, 7), (8191, 13)])
+@pytest.mark.parametrize("r", [2, 3, 5, 6, 7, 12, 15, 16])
+def test_algorithm8_bucket_and_sign_counts(p, b, r):
+    """eq. prix0 / prixneq0: over h in [p], bucket 0 gets 2 ceil(2^(b-1)/r) - 1 values and
+    every other bucket 2 floor(2^(b-1)/r) or 2 ceil(2^(b-1)/r); the sign bit is 1 for
+    2^(b-1) values; Lemma ix-r-dist's bounds hold."""
+    if r > 1 << (b - 1):
+        pytest.skip("r > 2^(b-1)")
+    bk, sg = _arb_split_all_h(p, b, r)
+    assert bk.min() >= 0 and bk.max() < r
+    cnt = np.bincount(bk, minlength=r)
+    half = 1 << (b - 1)
+    lo, hi = half // r, -(-half // r)
+    assert cnt[0] == 2 * hi - 1
+    assert all(c in (2 * lo, 2 * hi) for c in cnt[1:])
+    assert (sg == -1).sum() == half and (sg == 1).sum() == half - 1   # s = 1 - 2a, a = bit b-1 of h+1
+    pr = Fraction(1, p)
+    assert cnt[0] * pr <= (1 + Fraction(r, 1 << b)) / r                       # eq. ix=0
+    assert sum(Fraction(int(c), p) ** 2 for c in cnt) <= (1 + Fraction(r, 1 << b) ** 2) / r   # eq. ix=iy
+
+
+@pytest.mark.parametrize("p,b", [(31, 5), (127, 7)])
+@pytest.mark.parametrize("r", [3, 5, 6])
+def test_algorithm8_sign_surplus_only_in_bucket_zero(p, b, r):
+    """Lemma remove-si-r-dist with A = [i_x = i]: summed over h in [p], s_x [i_x = i] is 0
+    for every bucket i != 0, and bucket 0 keeps a surplus of -1 (h + 1 = 2^(b-1) has sign
+    bit 1 and j = 0, with no partner h + 1 = 0).  So E[s_x [i_x = 0]] = -1/p: the lemma's
+    E[A | i_x = 0]/p up to the global sign of its opposite convention s = 2a - 1."""
+    bk, sg = _arb_split_all_h(p, b, r)
+    for i in range(r):
+        assert sg[bk == i].sum() == (-1 if i == 0 else 0)
+
+
+@pytest.mark.parametrize("r", [3, 5, 6, 7])
+@pytest.mark.parametrize("stream", STREAMS)
+def test_theorem_arb_r_exact_mean_and_variance_p31(r, stream):
+    """Theorem h-and-s-p-arb-r over all of Z_31^4 (u = 16 keys, 1 < r <= u/2,
+    p = 31 > u): E[X] = F2 + (F1^2 - F2)/p^2 exactly, |E[X] - F2| <= F2 (n-1)/p^2 and
+    Var[X] < 2 (1 + (r/2^b)^2) F2^2 / r."""
+    p, b = 31, 5
+    keys, weights = stream
+    F1, F2, n = _moments(keys, weights)
+    s1, s2 = O.enum_estimate_moments(p, b, 4, O.ARB_R, r, keys, weights)
+    N = p ** 4
+    assert s1 == N * F2 + p * p * (F1 * F1 - F2)
+    assert abs(Fraction(s1, N) - F2) <= Fraction(F2 * (n - 1), p * p)
+    var = Fraction(s2, N) - Fraction(s1, N) ** 2
+    assert var < 2 * (1 + Fraction(r, 1 << b) ** 2) * F2 * F2 / r
+
+
+def test_algorithm8_with_power_of_two_r_selects_bits():
+    """For r = 2^l, floor(r j / 2^(b-1)) is the top l bits of the low b-1 bits of h + 1: a
+    plain bit selection of the hash value, checked against the independent hash functions
+    for p = 2^61 - 1 and 2^89 - 1 (identity polynomial h(x) = x and random polynomials)."""
+    keys = [0, 1, 5, (1 << 59) + 12345, (1 << 60) - 1]
+    for l in (1, 4, 10):
+        r = 1 << l
+        for prime, b in ((O.PRIME_P61, 61), (O.PRIME_P89, 89)):
+            coeffs = O.coeffs_from_seed(prime, 2, O.ARB_R, seed=77)
+            for row in range(2):
+                for x in keys:
+                    bk, s = O.bucket_sign(prime, O.ARB_R, r, coeffs, row, x)
+                    if prime == O.PRIME_P61:
+                        h = O.hash_small(O.P61, coeffs[row * 4:(row + 1) * 4], x)
+                    else:
+                        h = O.hash_p89(coeffs.reshape(-1, 2)[row * 4:(row + 1) * 4], x)
+                    hx = h + 1
+                    assert bk == (hx & ((1 << (b - 1)) - 1)) >> (b - 1 - l)
+                    assert s == 1 - 2 * ((hx >> (b - 1)) & 1)
+
+
+def test_arb_r_invalid_counts_and_linearity():
+    small = [1, 2, 3, 4]
+    for r in (0, 1, 17):          # r = 17 > 2^(b-1) for b = 5
+        with pytest.raises(O.OracleError):
+            O.cs_update(O.PRIME_P61, O.ARB_R, 1, r, small, [1], [1], p=31, b=5)
+    coeffs = O.coeffs_from_seed(O.PRIME_P61, 3, O.ARB_R, seed=5)
+    keys = list(range(1000, 1400))
+    w = [(i * 37) % 201 - 100 for i in range(400)]
+    whole = O.cs_update(O.PRIME_P61, O.ARB_R, 3, 1000, coeffs, keys, w)
+    part = O.cs_update(O.PRIME_P61, O.ARB_R, 3, 1000, coeffs, keys[:150], w[:150])
+    O.cs_update(O.PRIME_P61, O.ARB_R, 3, 1000, coeffs, keys[150:], w[150:], table=part)
+    assert np.array_equal(whole, part)
+    assert int(np.abs(whole).sum()) > 0
