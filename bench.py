@@ -73,8 +73,9 @@ DIVMOD_WORKLOADS = {
 HERE = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic.json")
 # The measured HBM traffic stands only for the kernels it was measured on.
-KERNEL_SOURCES = ["paper_2008_08654_amd/csrc/" + f for f in
-                  ("sketch_kernels.hip", "sketch_kernels.hpp", "field.hpp", "divmod_kernels.hip", "mcs_host.cpp")]
+KERNEL_SOURCES = sorted("paper_2008_08654_amd/csrc/" + f for f in os.listdir(os.path.join(HERE, "paper_2008_08654_amd",
+                                                                                           "csrc"))
+                        if f.endswith((".hip", ".hpp")) or f == "mcs_host.cpp")
 
 
 def kernel_sources_sha256() -> str:

@@ -46,7 +46,9 @@ typedef enum {
 typedef enum {
   CS_TWO_FOR_ONE = 0,     /* one hash h per row: a = bit 0 of h, i = bits 1..l of h */
   CS_TWO_FOR_ONE_MSB = 1, /* Algorithm 3 as printed: i = low l bits, a = top bit b-1 */
-  CS_TWO_POLY = 2         /* two independent hashes per row: i = low l bits of h1, a = bit 0 of h2 */
+  CS_TWO_POLY = 2,        /* two independent hashes per row: i = low l bits of h1, a = bit 0 of h2 */
+  CS_ARB_R = 3            /* any bucket count r, Algorithm 8 (Section 3.3): with h' = h + 1,
+                             i = floor(r * (h' mod 2^(b-1)) / 2^(b-1)), a = bit b-1 of h' */
 } cs_mode;
 
 typedef enum { CS_U32 = 0, CS_U64 = 1, CS_I32 = 2, CS_I64 = 3 } cs_dtype;
@@ -62,7 +64,9 @@ typedef struct cs_sketch cs_sketch; /* opaque, library-owned */
  *   rows     >= 1
  *   buckets  = 2^l; l <= b-1 for the two-for-one modes (sign bit and bucket
  *            bits must be distinct: premise of Lemma remove-si), l <= b for
- *            CS_TWO_POLY; in every mode l <= 30
+ *            CS_TWO_POLY; in every mode l <= 30.  CS_ARB_R takes any count r in
+ *            [2, 2^30]; its table rows are then padded to the next power of
+ *            two (the padding counters stay zero)
  *   prime    CS_P61 or CS_P89
  *   seed     expanded with SplitMix64 into coefficients uniform in [p]
  *            (p61: low 61 bits of a draw, draws equal to p rejected; p89: one
@@ -130,10 +134,12 @@ cs_status cs_query(cs_sketch* s, const void* keys, cs_dtype key_type, uint64_t n
 enum { CS_PATH_AUTO = 0, CS_PATH_LDS = 1, CS_PATH_GLOBAL = 2, CS_PATH_BINNED = 3, CS_PATH_BINNED_NOCOMBINE = 4 };
 cs_status cs_set_update_path(cs_sketch* s, int path);
 
-/* Copies the rows*buckets counters (row-major) to host memory; synchronises. */
+/* Copies the rows*buckets counters (row-major, no padding) to host memory;
+ * synchronises. */
 cs_status cs_read_counters(cs_sketch* s, int64_t* host_dst, hipStream_t stream);
-/* Device pointer to the counter table (rows*buckets int64, row-major), owned
- * by the sketch; valid until cs_destroy. */
+/* Device pointer to the counter table (rows rows of int64, row-major, row
+ * pitch = buckets rounded up to a power of two), owned by the sketch; valid
+ * until cs_destroy. */
 cs_status cs_table_device(cs_sketch* s, int64_t** dev_table);
 /* Copies the coefficients (layout as in cs_create_with_coeffs) to host. */
 cs_status cs_read_coeffs(cs_sketch* s, uint64_t* host_dst);
@@ -157,7 +163,8 @@ cs_status cs_sync(cs_sketch* s, hipStream_t stream);
  *              x < 2^128 by Theorem simple-div) and Algorithm 6; x has 2 limbs,
  *              x < p*2^64 (so the quotient fits one limb); quot and rem 1 limb.
  * Limbs are little-endian uint64.  x, quot and rem are device pointers; quot
- * or rem may be NULL to skip that output.  A value outside the domain sets a
+ * or rem may be NULL to skip that output.  Two-limb arrays (x for CS_P61 and
+ * CS_P64_59, quot and rem for CS_P89) must be 16-byte aligned (CS_EINVAL).  A value outside the domain sets a
  * device flag that the call returns as CS_EDOMAIN on the next
  * mersenne_status call (outputs for such values are unspecified).  Enqueued
  * on `stream`.
@@ -172,6 +179,22 @@ cs_status mersenne_mod(cs_prime prime, const uint64_t* x, uint64_t n, uint64_t* 
  * (CS_P89: shift-and-subtract long division). */
 cs_status mersenne_divmod_naive(cs_prime prime, const uint64_t* x, uint64_t n, uint64_t* quot,
                                 uint64_t* rem, hipStream_t stream);
+/* Most uniform maps of hash values v in [p] to [r] buckets (Section 1.4, Lemma
+ * most-uniform; for 2^64-59 the note on bucket counts in Section 1.5):
+ *   CS_MAP_EXACT:    floor(v * r / p) by the branch-free division of
+ *                    Algorithm 4 (Mersenne) or Algorithms 5 and 6 (2^64-59);
+ *   CS_MAP_MERSENNE: floor((v + 1) * r / 2^b), eq. most-uniform (Mersenne
+ *                    primes only).
+ *   v    device; one uint64 per value (CS_P61, CS_P64_59) or two limbs
+ *        (CS_P89, 16-byte aligned); each v < p, else the domain flag is set
+ *        (mersenne_status)
+ *   r    1 <= r < 2^32
+ *   out  device, n uint32 buckets
+ * Enqueued on `stream`. */
+enum { CS_MAP_EXACT = 0, CS_MAP_MERSENNE = 1 };
+cs_status mersenne_bucket_map(cs_prime prime, int method, const uint64_t* v, uint64_t n, uint64_t r, uint32_t* out,
+                              hipStream_t stream);
+
 /* Synchronises `stream` and returns (and clears) the domain flag of the
  * quotient/remainder calls on the current device. */
 cs_status mersenne_status(hipStream_t stream);

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(HERE, "libmcs.so")
 # enums mirrored from include/mcs.h
 CS_OK, CS_EINVAL, CS_ENOMEM, CS_EDOMAIN, CS_EOVERFLOW, CS_EDEVICE, CS_EBUSY = 0, -1, -2, -3, -4, -5, -6
 CS_P61, CS_P89, CS_P64_59 = 1, 2, 3
-CS_TWO_FOR_ONE, CS_TWO_FOR_ONE_MSB, CS_TWO_POLY = 0, 1, 2
+CS_TWO_FOR_ONE, CS_TWO_FOR_ONE_MSB, CS_TWO_POLY, CS_ARB_R = 0, 1, 2, 3
+CS_MAP_EXACT, CS_MAP_MERSENNE = 0, 1
 CS_U32, CS_U64, CS_I32, CS_I64 = 0, 1, 2, 3
 CS_PATH_AUTO, CS_PATH_LDS, CS_PATH_GLOBAL, CS_PATH_BINNED, CS_PATH_BINNED_NOCOMBINE = 0, 1, 2, 3, 4
 
@@ -65,6 +66,7 @@ def lib() -> ctypes.CDLL:
             "mersenne_mod": [i32, P, u64, P, P],
             "mersenne_divmod_naive": [i32, P, u64, P, P, P],
             "mersenne_status": [P],
+            "mersenne_bucket_map": [i32, i32, P, u64, u64, P, P],
             "cs_batch_create": [P, u32, i32, i32, P, P],
             "cs_batch_update": [P, P],
             "cs_batch_autotune": [P, P, P],
@@ -438,6 +440,12 @@ def mersenne_div(prime: int, x, quot, stream=None):
 
 def mersenne_mod(prime: int, x, rem, stream=None):
     _check(lib().mersenne_mod(prime, _dev_ptr(x), x.shape[0], _dev_ptr(rem), _stream(stream)))
+
+
+def mersenne_bucket_map(prime: int, v, r: int, out, method: int = CS_MAP_EXACT, stream=None):
+    """Buckets in [r] of hash values v < p (uint64 tensor of shape (n,), or (n, 2) limbs for
+    2^89 - 1) into out (int32 tensor of n uint32 bit patterns)."""
+    _check(lib().mersenne_bucket_map(prime, method, _dev_ptr(v), v.shape[0], r, _dev_ptr(out), _stream(stream)))
 
 
 def mersenne_status(stream=None):

@@ -2,6 +2,8 @@
 // pseudo-Mersenne primes (Section 1.5 and Section 4 of Ahle, Knudsen, Thorup).
 // Streaming, HBM-bound: each thread handles kUnroll independent values per
 // iteration so several loads are in flight; the arithmetic is field.hpp's.
+#include <algorithm>
+
 #include "sketch_kernels.hpp"
 
 namespace mcs {
@@ -130,6 +132,91 @@ static uint32_t grid_for(uint64_t n, uint64_t per_thread) {
   if (blocks > 65536) blocks = 65536;
   if (blocks == 0) blocks = 1;
   return (uint32_t)blocks;
+}
+
+// Most uniform maps of hash values v in [p] to [r] buckets (Section 1.4 and
+// Section 1.5):
+//   exact     floor(v r / p): the quotient of the product v r (< p 2^32, inside
+//             every divmod domain) by Algorithm 4 or Algorithms 5 and 6
+//   mersenne  ((v + 1) r) >> b (eq. most-uniform)
+// v >= p sets the domain flag (its bucket is unspecified).
+template <int PRIME, bool FAST>
+__global__ __launch_bounds__(kBlock) void k_bucket_map(const uint64_t* __restrict__ v, uint64_t n, uint32_t r,
+                                                       uint32_t* __restrict__ out, uint32_t* flags) {
+  typedef unsigned __int128 u128;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  uint32_t bad = 0;
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock + threadIdx.x; base < n; base += stride * kUnroll) {
+    uint64_t lo[kUnroll], hi[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const uint64_t i = base + u * stride;
+      lo[u] = hi[u] = 0;
+      if (i < n) {
+        if (PRIME == kPrime89) {
+          const ulonglong2 w = reinterpret_cast<const ulonglong2*>(v)[i];
+          lo[u] = w.x;
+          hi[u] = w.y;
+        } else {
+          lo[u] = v[i];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const uint64_t i = base + u * stride;
+      uint32_t b;
+      if (PRIME == kPrime61) {
+        bad |= (uint32_t)(lo[u] >= (1ull << 61) - 1);
+        if (FAST) {
+          b = (uint32_t)((((u128)(lo[u] + 1)) * r) >> 61);
+        } else {
+          const u128 x = (u128)lo[u] * r;
+          uint64_t q, rem;
+          p61_divmod((uint64_t)x, (uint64_t)(x >> 64), q, rem);
+          b = (uint32_t)q;
+        }
+      } else if (PRIME == kPrime64c) {
+        bad |= (uint32_t)(lo[u] >= 0xFFFFFFFFFFFFFFFFull - 58);
+        const u128 x = (u128)lo[u] * r;
+        uint64_t q, rem;
+        p64c_divmod((uint64_t)x, (uint64_t)(x >> 64), q, rem);
+        b = (uint32_t)q;
+      } else {
+        bad |= (uint32_t)(hi[u] > (1ull << 25) - 1 || (hi[u] == (1ull << 25) - 1 && lo[u] == ~0ull));
+        const u128 vv = ((u128)hi[u] << 64) | lo[u];
+        if (FAST) {
+          b = (uint32_t)(((vv + 1) * r) >> 89);
+        } else {
+          const u128 x = vv * r;  // < 2^121
+          uint64_t q0, q1, r0, r1;
+          p89_divmod((uint64_t)x, (uint64_t)(x >> 64), 0, q0, q1, r0, r1);
+          b = (uint32_t)q0;
+        }
+      }
+      if (i < n) out[i] = b;
+    }
+  }
+  if (__any(bad)) {
+    if (bad) atomicOr(flags, kFlagDomain);
+  }
+}
+
+hipError_t launch_bucket_map(int prime, bool fast, const uint64_t* v, uint64_t n, uint32_t r, uint32_t* out,
+                             uint32_t* flags, uint32_t cus, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const uint64_t want = (n + (uint64_t)kBlock * kUnroll - 1) / ((uint64_t)kBlock * kUnroll);
+  const uint32_t g = (uint32_t)std::min<uint64_t>(want, (uint64_t)cus * 16);
+  if (prime == kPrime61) {
+    if (fast) hipLaunchKernelGGL((k_bucket_map<kPrime61, true>), dim3(g), dim3(kBlock), 0, st, v, n, r, out, flags);
+    else hipLaunchKernelGGL((k_bucket_map<kPrime61, false>), dim3(g), dim3(kBlock), 0, st, v, n, r, out, flags);
+  } else if (prime == kPrime89) {
+    if (fast) hipLaunchKernelGGL((k_bucket_map<kPrime89, true>), dim3(g), dim3(kBlock), 0, st, v, n, r, out, flags);
+    else hipLaunchKernelGGL((k_bucket_map<kPrime89, false>), dim3(g), dim3(kBlock), 0, st, v, n, r, out, flags);
+  } else {
+    hipLaunchKernelGGL((k_bucket_map<kPrime64c, false>), dim3(g), dim3(kBlock), 0, st, v, n, r, out, flags);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_divmod(int prime, bool naive, const uint64_t* x, uint64_t n, uint64_t* quot, uint64_t* rem,

@@ -125,9 +125,17 @@ static cs_status check_shape(uint32_t rows, uint64_t buckets, cs_prime prime, cs
                              int* log2m) {
   if (rows == 0 || rows > kMaxRows) return fail(CS_EINVAL, "rows must be in [1, %u]", kMaxRows);
   if (prime != CS_P61 && prime != CS_P89) return fail(CS_EINVAL, "sketch prime must be CS_P61 or CS_P89");
-  if (mode != CS_TWO_FOR_ONE && mode != CS_TWO_FOR_ONE_MSB && mode != CS_TWO_POLY)
+  if (mode != CS_TWO_FOR_ONE && mode != CS_TWO_FOR_ONE_MSB && mode != CS_TWO_POLY && mode != CS_ARB_R)
     return fail(CS_EINVAL, "unknown mode %d", (int)mode);
   if (k != 2 && k != 4 && k != 8) return fail(CS_EINVAL, "k must be 2, 4 or 8");
+  if (mode == CS_ARB_R) {  // any count; rows are padded to the next power of two
+    if (buckets < 2 || buckets > (1ull << kMaxLog2m))
+      return fail(CS_EINVAL, "buckets must be in [2, 2^%u]", kMaxLog2m);
+    int l = 0;
+    while ((1ull << l) < buckets) ++l;
+    *log2m = l;
+    return CS_OK;
+  }
   int l = log2_exact(buckets);
   if (l < 0) return fail(CS_EINVAL, "buckets must be a power of two");
   if ((uint32_t)l > kMaxLog2m) return fail(CS_EINVAL, "buckets must be at most 2^%u", kMaxLog2m);
@@ -157,6 +165,7 @@ static cs_status create_common(uint32_t rows, uint64_t buckets, cs_prime prime, 
   if (!s) return fail(CS_ENOMEM, "host allocation");
   s->rows = rows;
   s->log2m = (uint32_t)l;
+  s->buckets = buckets;
   s->prime = prime;
   s->mode = mode;
   s->k = k;
@@ -167,10 +176,10 @@ static cs_status create_common(uint32_t rows, uint64_t buckets, cs_prime prime, 
   for (size_t i = 0; i < ncoef; ++i) {
     if (prime == CS_P61) {
       uint64_t v = coeffs[i];
-      rec[i] = make_uint4((uint32_t)v, (uint32_t)(v >> 32), 0, 0);
+      rec[i] = make_uint4((uint32_t)v, (uint32_t)(v >> 32), 0, (uint32_t)buckets);
     } else {
       uint64_t lo = coeffs[2 * i], hi = coeffs[2 * i + 1];
-      rec[i] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, 0);
+      rec[i] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)buckets);
     }
   }
   const size_t cells = (size_t)rows << l;
@@ -473,7 +482,12 @@ extern "C" cs_status cs_sync(cs_sketch* s, hipStream_t stream) {
 extern "C" cs_status cs_read_counters(cs_sketch* s, int64_t* host_dst, hipStream_t stream) {
   if (!s || !host_dst) return fail(CS_EINVAL, "sketch or destination is NULL");
   HIP_TRY(hipStreamSynchronize(stream));
-  HIP_TRY(hipMemcpy(host_dst, s->d_table, ((size_t)s->rows << s->log2m) * 8, hipMemcpyDeviceToHost));
+  if (s->buckets == (1ull << s->log2m)) {
+    HIP_TRY(hipMemcpy(host_dst, s->d_table, ((size_t)s->rows << s->log2m) * 8, hipMemcpyDeviceToHost));
+  } else {  // drop the padding of each row
+    HIP_TRY(hipMemcpy2D(host_dst, s->buckets * 8, s->d_table, (size_t)8 << s->log2m, s->buckets * 8, s->rows,
+                        hipMemcpyDeviceToHost));
+  }
   uint32_t flags = 0;
   HIP_TRY(hipMemcpy(&flags, s->d_flags, 4, hipMemcpyDeviceToHost));
   return sticky(s, flags);
@@ -495,7 +509,7 @@ extern "C" cs_status cs_info(const cs_sketch* s, uint32_t* rows, uint64_t* bucke
                              uint32_t* k) {
   if (!s) return fail(CS_EINVAL, "sketch is NULL");
   if (rows) *rows = s->rows;
-  if (buckets) *buckets = 1ull << s->log2m;
+  if (buckets) *buckets = s->buckets;
   if (prime) *prime = s->prime;
   if (mode) *mode = s->mode;
   if (k) *k = s->k;
@@ -512,7 +526,7 @@ extern "C" cs_status cs_reset(cs_sketch* s, hipStream_t stream) {
 
 extern "C" cs_status cs_merge(cs_sketch* dst, const cs_sketch* src, hipStream_t stream) {
   if (!dst || !src) return fail(CS_EINVAL, "sketch is NULL");
-  if (dst->rows != src->rows || dst->log2m != src->log2m || dst->prime != src->prime || dst->mode != src->mode ||
+  if (dst->rows != src->rows || dst->buckets != src->buckets || dst->prime != src->prime || dst->mode != src->mode ||
       dst->k != src->k || dst->h_coeffs != src->h_coeffs)
     return fail(CS_EINVAL, "sketches differ in shape or coefficients");
   hipError_t e = launch_add_tables((unsigned long long*)dst->d_table, (const unsigned long long*)src->d_table,
@@ -549,6 +563,10 @@ static cs_status divmod_common(cs_prime prime, const uint64_t* x, uint64_t n, ui
   if (n == 0) return CS_OK;
   if (!x) return fail(CS_EINVAL, "x is NULL");
   if (!quot && !rem) return fail(CS_EINVAL, "quot and rem are both NULL");
+  // the kernels move two-limb values as 16-byte vectors
+  if (prime != CS_P89 && ((uintptr_t)x & 15)) return fail(CS_EINVAL, "x must be 16-byte aligned");
+  if (prime == CS_P89 && (((uintptr_t)quot & 15) || ((uintptr_t)rem & 15)))
+    return fail(CS_EINVAL, "quot and rem must be 16-byte aligned for CS_P89");
   uint32_t* flags = divmod_flags();
   if (!flags) return fail(CS_ENOMEM, "flag allocation");
   int p = prime == CS_P61 ? kPrime61 : prime == CS_P89 ? kPrime89 : kPrime64c;
@@ -573,6 +591,27 @@ extern "C" cs_status mersenne_divmod_naive(cs_prime prime, const uint64_t* x, ui
                                            uint64_t* rem, hipStream_t stream) {
   return divmod_common(prime, x, n, quot, rem, stream, true);
 }
+extern "C" cs_status mersenne_bucket_map(cs_prime prime, int method, const uint64_t* v, uint64_t n, uint64_t r,
+                                         uint32_t* out, hipStream_t stream) {
+  if (prime != CS_P61 && prime != CS_P89 && prime != CS_P64_59) return fail(CS_EINVAL, "unknown prime %d", (int)prime);
+  if (method != CS_MAP_EXACT && method != CS_MAP_MERSENNE) return fail(CS_EINVAL, "unknown map %d", method);
+  if (method == CS_MAP_MERSENNE && prime == CS_P64_59)
+    return fail(CS_EINVAL, "the (v+1)r >> b map is most uniform only for Mersenne primes");
+  if (r == 0 || r >= (1ull << 32)) return fail(CS_EINVAL, "r must be in [1, 2^32)");
+  if (n == 0) return CS_OK;
+  if (!v || !out) return fail(CS_EINVAL, "v or out is NULL");
+  if (prime == CS_P89 && ((uintptr_t)v & 15)) return fail(CS_EINVAL, "v must be 16-byte aligned for CS_P89");
+  uint32_t* flags = divmod_flags();
+  if (!flags) return fail(CS_ENOMEM, "flag allocation");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  const int pk = prime == CS_P61 ? kPrime61 : prime == CS_P89 ? kPrime89 : kPrime64c;
+  hipError_t e = launch_bucket_map(pk, method == CS_MAP_MERSENNE, v, n, (uint32_t)r, out, flags,
+                                   (uint32_t)device_info(dev).cus, stream);
+  if (e != hipSuccess) return hip_fail(e, "bucket map launch");
+  return CS_OK;
+}
+
 extern "C" cs_status mersenne_status(hipStream_t stream) {
   uint32_t* flags = divmod_flags();
   if (!flags) return fail(CS_ENOMEM, "flag allocation");

@@ -11,7 +11,8 @@
 
 struct cs_sketch {
   uint32_t rows = 0;
-  uint32_t log2m = 0;
+  uint32_t log2m = 0;        // table row pitch is 2^log2m counters
+  uint64_t buckets = 0;      // bucket count r (2^log2m except in CS_ARB_R)
   cs_prime prime = CS_P61;
   cs_mode mode = CS_TWO_FOR_ONE;
   uint32_t k = 4;

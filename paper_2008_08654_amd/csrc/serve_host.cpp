@@ -378,7 +378,7 @@ extern "C" cs_status cs_server_create(cs_prime prime, cs_mode mode, uint32_t k, 
   if (!out) return fail(CS_EINVAL, "out is NULL");
   *out = nullptr;
   if (prime != CS_P61 && prime != CS_P89) return fail(CS_EINVAL, "sketches use CS_P61 or CS_P89");
-  if (mode != CS_TWO_FOR_ONE && mode != CS_TWO_FOR_ONE_MSB && mode != CS_TWO_POLY)
+  if (mode != CS_TWO_FOR_ONE && mode != CS_TWO_FOR_ONE_MSB && mode != CS_TWO_POLY && mode != CS_ARB_R)
     return fail(CS_EINVAL, "unknown mode %d", (int)mode);
   if (k != 2 && k != 4 && k != 8) return fail(CS_EINVAL, "k must be 2, 4 or 8");
   if (key_type != CS_U32 && key_type != CS_U64) return fail(CS_EINVAL, "key type must be CS_U32 or CS_U64");
@@ -434,8 +434,8 @@ extern "C" cs_status cs_server_create(cs_prime prime, cs_mode mode, uint32_t k, 
 extern "C" cs_status cs_server_admit(cs_server* S, uint32_t rows, uint64_t buckets, uint64_t seed, uint32_t* tenant) {
   if (!S || !tenant) return fail(CS_EINVAL, "server or tenant is NULL");
   if (rows < 1 || rows > 16) return fail(CS_EINVAL, "served sketches have 1..16 rows, got %u", rows);
-  if (buckets < 2 || buckets > (1u << 18) || (buckets & (buckets - 1)))
-    return fail(CS_EINVAL, "served sketches have a power-of-two bucket count up to 2^18");
+  if (buckets < 2 || buckets > (1u << 18) || (S->cmode != CS_ARB_R && (buckets & (buckets - 1))))
+    return fail(CS_EINVAL, "served sketches have up to 2^18 buckets, a power of two except in CS_ARB_R");
   uint32_t l = 0;
   while ((1ull << l) < buckets) ++l;
   const size_t bytes = sketch_device_bytes(rows, l, S->cmode, S->k);

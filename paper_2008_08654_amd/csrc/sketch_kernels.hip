@@ -1,675 +1,13 @@
-// sketch_kernels.hip -- Count Sketch kernels for gfx950 (Algorithm 2 of Ahle,
-// Knudsen, Thorup, "The Power of Hashing with Mersenne Primes").
-//
-// Per key and row: Horner evaluation of the row's polynomial over p
-// (Algorithm 1, field.hpp), branch-free final reduction (Algorithm 4), the
-// bucket/sign split (Algorithm 3 or the low-bit layout of Section 1.2.1), and
-// a signed int64 add into the row's counters.
-//
-// Coefficients live in device memory as one 16-byte record per coefficient
-// (32-bit limbs w0, w1, w2, 0), indexed [row][poly][i]; the row loop is the
-// outer loop so each row's coefficients are wave-uniform scalar loads.
+// sketch_kernels.hip -- the non-template Count Sketch kernels (pass 2 of the
+// two-pass update, F2 estimates, table fill and add) and the dispatch from
+// runtime (prime, mode) to the per-pair launchers instantiated in
+// sketch_p*_*.hip.
 #include <algorithm>
 
+#include "device_util.hpp"
 #include "sketch_kernels.hpp"
 
 namespace mcs {
-
-// ---------------------------------------------------------------------------
-// hashing of one key in one row
-// ---------------------------------------------------------------------------
-// A row's coefficients, read once per row and kept in scalar registers
-// (readfirstlane): all lanes hash with the same polynomial.
-template <int K, int NP>
-struct RowCoeffs {
-  uint32_t w[NP * K][3];
-};
-
-template <int K, int NP>
-__device__ __forceinline__ RowCoeffs<K, NP> load_row_coeffs(const uint4* __restrict__ c) {
-  RowCoeffs<K, NP> rc;
-#pragma unroll
-  for (int i = 0; i < NP * K; ++i) {
-    const uint4 v = c[i];
-    rc.w[i][0] = __builtin_amdgcn_readfirstlane(v.x);
-    rc.w[i][1] = __builtin_amdgcn_readfirstlane(v.y);
-    rc.w[i][2] = __builtin_amdgcn_readfirstlane(v.z);
-  }
-  return rc;
-}
-
-template <int K, int NP>
-__device__ __forceinline__ uint64_t hash61_x32(const RowCoeffs<K, NP>& c, int q, uint32_t x) {
-  F61 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
-#pragma unroll
-  for (int i = K - 2; i >= 0; --i) y = p61_step_x32(y, x, F61{c.w[q * K + i][0], c.w[q * K + i][1]});
-  return p61_final(y);
-}
-
-template <int K, int NP>
-__device__ __forceinline__ uint64_t hash61_x64(const RowCoeffs<K, NP>& c, int q, uint32_t x0, uint32_t x1) {
-  F61 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
-#pragma unroll
-  for (int i = K - 2; i >= 0; --i) y = p61_step_x64(y, x0, x1, F61{c.w[q * K + i][0], c.w[q * K + i][1]});
-  return p61_final(y);
-}
-
-template <int K, int NP>
-__device__ __forceinline__ F89 hash89(const RowCoeffs<K, NP>& c, int q, uint32_t x0, uint32_t x1) {
-  F89 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1], c.w[q * K + K - 1][2]};
-#pragma unroll
-  for (int i = K - 2; i >= 0; --i)
-    y = p89_step(y, x0, x1, F89{c.w[q * K + i][0], c.w[q * K + i][1], c.w[q * K + i][2]});
-  return p89_final(y);
-}
-
-// Bucket and sign bit of key (x0, x1) under a row's coefficients.  WIDE
-// selects the two-limb key path for p61.
-template <int PRIME, int MODE, int K, bool WIDE, int NP>
-__device__ __forceinline__ void bucket_sign(const RowCoeffs<K, NP>& c, uint32_t x0, uint32_t x1, uint32_t log2m,
-                                            uint32_t& bucket, uint32_t& a) {
-  const uint32_t mask = (1u << log2m) - 1u;
-  if constexpr (PRIME == kPrime61) {
-    uint64_t h = WIDE ? hash61_x64<K, NP>(c, 0, x0, x1) : hash61_x32<K, NP>(c, 0, x0);
-    if constexpr (MODE == kTwoForOne) {
-      a = (uint32_t)h & 1u;
-      bucket = ((uint32_t)h >> 1) & mask;
-    } else if constexpr (MODE == kTwoForOneMsb) {
-      a = (uint32_t)(h >> 60) & 1u;
-      bucket = (uint32_t)h & mask;
-    } else {
-      uint64_t h2 = WIDE ? hash61_x64<K, NP>(c, 1, x0, x1) : hash61_x32<K, NP>(c, 1, x0);
-      a = (uint32_t)h2 & 1u;
-      bucket = (uint32_t)h & mask;
-    }
-  } else {
-    F89 h = hash89<K, NP>(c, 0, x0, x1);
-    if constexpr (MODE == kTwoForOne) {
-      a = h.w0 & 1u;
-      bucket = (h.w0 >> 1) & mask;
-    } else if constexpr (MODE == kTwoForOneMsb) {
-      a = (h.w2 >> 24) & 1u;
-      bucket = h.w0 & mask;
-    } else {
-      F89 h2 = hash89<K, NP>(c, 1, x0, x1);
-      a = h2.w0 & 1u;
-      bucket = h.w0 & mask;
-    }
-  }
-}
-
-template <typename KeyT>
-__device__ __forceinline__ void load_key(const KeyT* __restrict__ keys, uint64_t i, uint32_t& x0, uint32_t& x1) {
-  if constexpr (sizeof(KeyT) == 4) {
-    x0 = keys[i];
-    x1 = 0;
-  } else {
-    uint64_t v = keys[i];
-    x0 = (uint32_t)v;
-    x1 = (uint32_t)(v >> 32);
-  }
-}
-
-template <typename WT>
-__device__ __forceinline__ int64_t load_weight(const WT* __restrict__ w, uint64_t i) {
-  return (int64_t)w[i];
-}
-
-__device__ __forceinline__ unsigned long long signed_weight(int64_t w, uint32_t a) {
-  return (unsigned long long)(a ? -w : w);
-}
-
-// ---------------------------------------------------------------------------
-// Single pass with the whole table in LDS.  Each block zeroes its private
-// table, processes a contiguous key range, then adds the non-zero partial
-// counters into the global table with coalesced int64 atomics.
-// ---------------------------------------------------------------------------
-// Zero the block's LDS table, add keys [begin, end) of `args` into it, then add
-// its non-zero counters into args.table.  Used by the single-sketch and the
-// batched kernels.
-template <int PRIME, int MODE, int K, typename KeyT, typename WT>
-__device__ __forceinline__ void lds_block_update(const UpdateArgs<KeyT, WT>& args, uint64_t begin, uint64_t end,
-                                                 unsigned long long* lds) {
-  const uint32_t cells = args.rows << args.log2m;
-  for (uint32_t i = threadIdx.x; i < cells; i += kBlock) lds[i] = 0;
-  __syncthreads();
-  constexpr int kKpt = kKeysPerThread;
-  constexpr int NP = MODE == kTwoPoly ? 2 : 1;
-  uint32_t bad = 0;
-
-  for (uint64_t base = begin; base < end; base += (uint64_t)kBlock * kKpt) {
-    uint32_t x0[kKpt], x1[kKpt];
-    int64_t wv[kKpt];
-    bool ok[kKpt];
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
-      ok[j] = i < end;
-      x0[j] = x1[j] = 0;
-      wv[j] = 0;
-      if (ok[j]) {
-        load_key(args.keys, i, x0[j], x1[j]);
-        wv[j] = load_weight(args.weights, i);
-      }
-    }
-    uint32_t any_hi = 0;
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) any_hi |= x1[j];
-    if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;  // key >= 2^60 breaks p >= 2u - 1
-    // wave-uniform choice of the one-limb key path (all keys < 2^32)
-    const bool wide = PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0);
-    for (uint32_t r = 0; r < args.rows; ++r) {
-      const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
-      unsigned long long* row = lds + ((size_t)r << args.log2m);
-      if (wide) {
-#pragma unroll
-        for (int j = 0; j < kKpt; ++j) {
-          uint32_t bk, a;
-          bucket_sign<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m, bk, a);
-          if (ok[j]) atomicAdd(&row[bk], signed_weight(wv[j], a));
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < kKpt; ++j) {
-          uint32_t bk, a;
-          bucket_sign<PRIME, MODE, K, false, NP>(c, x0[j], x1[j], args.log2m, bk, a);
-          if (ok[j]) atomicAdd(&row[bk], signed_weight(wv[j], a));
-        }
-      }
-    }
-  }
-  if (bad) atomicOr(args.flags, kFlagDomain);
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < cells; i += kBlock) {
-    unsigned long long v = lds[i];
-    if (v) atomicAdd(&args.table[i], v);
-  }
-}
-
-template <int PRIME, int MODE, int K, typename KeyT, typename WT>
-__global__ __launch_bounds__(kBlock) void k_update_lds(UpdateArgs<KeyT, WT> args) {
-  extern __shared__ unsigned long long lds[];
-  const uint64_t begin = (uint64_t)blockIdx.x * args.keys_per_block;
-  const uint64_t end = min(args.n, begin + args.keys_per_block);
-  lds_block_update<PRIME, MODE, K, KeyT, WT>(args, begin, end, lds);
-}
-
-// ---------------------------------------------------------------------------
-// Table in global memory, one device-scope int64 atomic per (key, row).
-// ---------------------------------------------------------------------------
-template <int PRIME, int MODE, int K, typename KeyT, typename WT>
-__device__ __forceinline__ void global_block_update(const UpdateArgs<KeyT, WT>& args, uint64_t begin, uint64_t end) {
-  constexpr int kKpt = kKeysPerThread;
-  constexpr int NP = MODE == kTwoPoly ? 2 : 1;
-  uint32_t bad = 0;
-  for (uint64_t base = begin; base < end; base += (uint64_t)kBlock * kKpt) {
-    uint32_t x0[kKpt], x1[kKpt];
-    int64_t wv[kKpt];
-    bool ok[kKpt];
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
-      ok[j] = i < end;
-      x0[j] = x1[j] = 0;
-      wv[j] = 0;
-      if (ok[j]) {
-        load_key(args.keys, i, x0[j], x1[j]);
-        wv[j] = load_weight(args.weights, i);
-      }
-    }
-    uint32_t any_hi = 0;
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) any_hi |= x1[j];
-    if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;
-    const bool wide = PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0);
-    for (uint32_t r = 0; r < args.rows; ++r) {
-      const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
-      unsigned long long* row = args.table + ((size_t)r << args.log2m);
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j) {
-        uint32_t bk, a;
-        if (wide)
-          bucket_sign<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m, bk, a);
-        else
-          bucket_sign<PRIME, MODE, K, false, NP>(c, x0[j], x1[j], args.log2m, bk, a);
-        if (ok[j]) atomicAdd(&row[bk], signed_weight(wv[j], a));
-      }
-    }
-  }
-  if (bad) atomicOr(args.flags, kFlagDomain);
-}
-
-template <int PRIME, int MODE, int K, typename KeyT, typename WT>
-__global__ __launch_bounds__(kBlock) void k_update_global(UpdateArgs<KeyT, WT> args) {
-  const uint64_t begin = (uint64_t)blockIdx.x * args.keys_per_block;
-  const uint64_t end = min(args.n, begin + args.keys_per_block);
-  global_block_update<PRIME, MODE, K, KeyT, WT>(args, begin, end);
-}
-
-// ---------------------------------------------------------------------------
-// Two-pass update for tables larger than LDS.
-//
-// The m buckets of a row are cut into G = m / R ranges of R = 2^log2r
-// buckets; (row, range) is a partition.
-// Pass 1 (k_bin): each block takes tiles of kBinTile keys.  For every row it
-// hashes the tile's keys and writes one 4-byte record per key into the
-// tile's region for that row, grouped by range.  A record is
-// (bucket mod R) << wbits | (signed weight mod 2^wbits), wbits = 32 - log2r;
-// a signed weight outside [-2^(wbits-1), 2^(wbits-1)) is added to the global
-// table directly with an atomic instead.  desc[tile][row][0..G] holds the
-// offsets of the groups in the region.
-// Pass 2 (k_accumulate): persistent blocks take (partition, slice of tiles)
-// items, add the item's records into an int64 LDS table of R counters, then
-// add the non-zero counters into the global table with coalesced atomics.
-// ---------------------------------------------------------------------------
-
-// Exclusive prefix of in[0..G) into out[0..G] by one wave (out[G] = total).
-__device__ __forceinline__ void wave_exclusive_scan(const uint32_t* in, uint32_t* out, uint32_t G, uint32_t lane) {
-  uint32_t carry = 0;
-  for (uint32_t b = 0; b < G; b += 64) {
-    const uint32_t v0 = b + lane < G ? in[b + lane] : 0u;
-    uint32_t v = v0;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      uint32_t t = __shfl_up(v, d, 64);
-      if (lane >= (uint32_t)d) v += t;
-    }
-    if (b + lane < G) out[b + lane] = carry + v - v0;
-    carry += __shfl(v, 63, 64);
-  }
-  if (lane == 0) out[G] = carry;
-}
-
-__device__ __forceinline__ uint32_t dedup_slot(uint32_t x0, uint32_t x1) {
-  return (x0 * 0x9E3779B1u) ^ (x1 * 0x85EBCA77u) ^ (x0 >> 15);
-}
-
-// LDS layout of k_bin: [combining: keys u64[T] | weights i64[T] | slots
-// u32[2T]] | stage u32[T] | hist u32[rows*G] | offs u32[G+1] | spare u32
-// (bin_lds_fixed_bytes() covers the parts before hist).
-template <int PRIME, int MODE, int K, typename KeyT, typename WT, bool DEDUP>
-__global__ __launch_bounds__(kBlock) void k_bin(BinArgs<KeyT, WT> args) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  constexpr uint32_t T = kBinTile;
-  unsigned long long* skey = (unsigned long long*)smem;          // DEDUP
-  long long* swt = (long long*)(smem + T * 8);                    // DEDUP
-  uint32_t* slots = (uint32_t*)(smem + T * 16);                   // DEDUP, 2T entries
-  uint32_t* stage = (uint32_t*)(smem + (DEDUP ? T * 24 : 0));
-  uint32_t* hist = stage + T;
-  const uint32_t G = 1u << args.log2g;
-  uint32_t* offs = hist + args.rows * G;
-  uint32_t* count = offs + G + 1;
-  const uint32_t log2r = args.log2r, wbits = 32u - log2r;
-  constexpr int kKpt = kBinKpt;
-  constexpr int NP = MODE == kTwoPoly ? 2 : 1;
-  const uint32_t rmask = (1u << log2r) - 1u;
-  const uint32_t wmask = (1u << wbits) - 1u;
-  const int64_t half = 1ll << (wbits - 1);
-  const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  uint32_t bad = 0;
-  for (uint32_t tile = blockIdx.x; tile < args.tiles; tile += gridDim.x) {
-    for (uint32_t i = threadIdx.x; i < args.rows * G; i += kBlock) hist[i] = 0;
-    if (DEDUP)
-      for (uint32_t i = threadIdx.x; i < 2 * T; i += kBlock) slots[i] = 0;
-    const uint64_t base = (uint64_t)tile * T;
-    uint32_t x0[kKpt], x1[kKpt];
-    int64_t wv[kKpt];
-    bool ok[kKpt];
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
-      ok[j] = i < args.n;
-      x0[j] = x1[j] = 0;
-      wv[j] = 0;
-      if (ok[j]) {
-        load_key(args.keys, i, x0[j], x1[j]);
-        wv[j] = load_weight(args.weights, i);
-      }
-    }
-    uint32_t any_hi = 0;
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) any_hi |= x1[j];
-    if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;
-    if constexpr (DEDUP) {
-      // Combine repeated keys of the tile: C[i(x)] += s(x) * sum of their
-      // weights is the same update (the sketch is linear).
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j) {
-        const uint32_t idx = j * kBlock + threadIdx.x;
-        skey[idx] = ((unsigned long long)x1[j] << 32) | x0[j];
-        swt[idx] = wv[j];
-      }
-      __syncthreads();
-      uint32_t own = 0;  // bit j: key j is the first copy in the tile
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j) {
-        if (!ok[j]) continue;
-        const uint32_t idx = j * kBlock + threadIdx.x;
-        const unsigned long long key = ((unsigned long long)x1[j] << 32) | x0[j];
-        uint32_t h = dedup_slot(x0[j], x1[j]) & (2 * T - 1);
-        for (uint32_t probe = 0; probe < 2 * T; ++probe) {
-          const uint32_t cur = atomicCAS(&slots[h], 0u, idx + 1);
-          if (cur == 0) {
-            own |= 1u << j;
-            break;
-          }
-          if (skey[cur - 1] == key) {
-            atomicAdd((unsigned long long*)&swt[cur - 1], (unsigned long long)wv[j]);
-            break;
-          }
-          h = (h + 1) & (2 * T - 1);
-        }
-      }
-      __syncthreads();
-      // compact the first copies (with their summed weights) to the front
-      unsigned long long ck[kKpt];
-      long long cw[kKpt];
-      uint32_t mine = 0;
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j) {
-        const uint32_t idx = j * kBlock + threadIdx.x;
-        ck[j] = skey[idx];
-        cw[j] = swt[idx];
-        mine += (own >> j) & 1u;
-      }
-      uint32_t v = mine;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += t;
-      }
-      if (lane == 63) stage[wave] = v;  // stage is free until the row loop
-      __syncthreads();
-      uint32_t pos = v - mine;
-      uint32_t total = 0;
-      for (uint32_t w = 0; w < kBlock / 64; ++w) {
-        const uint32_t c = stage[w];
-        if (w < wave) pos += c;
-        total += c;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j)
-        if ((own >> j) & 1u) {
-          skey[pos] = ck[j];
-          swt[pos] = cw[j];
-          ++pos;
-        }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j) {
-        const uint32_t e = j * kBlock + threadIdx.x;
-        ok[j] = e < total;
-        const unsigned long long key = ok[j] ? skey[e] : 0ull;
-        x0[j] = (uint32_t)key;
-        x1[j] = (uint32_t)(key >> 32);
-        wv[j] = ok[j] ? swt[e] : 0;
-      }
-    }
-    const bool wide = PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0);
-    __syncthreads();
-    for (uint32_t r = 0; r < args.rows; ++r) {
-      const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
-      uint32_t rec[kKpt], grp[kKpt], tick[kKpt];
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j) {
-        uint32_t bk, a;
-        if (wide)
-          bucket_sign<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m, bk, a);
-        else
-          bucket_sign<PRIME, MODE, K, false, NP>(c, x0[j], x1[j], args.log2m, bk, a);
-        int64_t sw = a ? -wv[j] : wv[j];
-        grp[j] = bk >> log2r;
-        rec[j] = ((bk & rmask) << wbits) | ((uint32_t)sw & wmask);
-        const bool fits = (uint64_t)(sw + half) < (2ull * (uint64_t)half);
-        tick[j] = 0xffffffffu;
-        if (ok[j] && sw != 0) {
-          if (fits)
-            tick[j] = atomicAdd(&hist[r * G + grp[j]], 1u);
-          else
-            atomicAdd(&args.table[((size_t)r << args.log2m) + bk], (unsigned long long)sw);
-        }
-      }
-      __syncthreads();
-      if (wave == 0) {
-        wave_exclusive_scan(hist + r * G, offs, G, lane);
-        uint32_t* d = args.desc + ((size_t)tile * args.rows + r) * (G + 1);
-        for (uint32_t g = lane; g <= G; g += 64) d[g] = offs[g];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j)
-        if (tick[j] != 0xffffffffu) stage[offs[grp[j]] + tick[j]] = rec[j];
-      __syncthreads();
-      // coalesced copy of the row's records to the tile region
-      const uint32_t nrec = offs[G];
-      uint4* out = (uint4*)(args.recs + ((size_t)tile * args.rows + r) * T);
-      const uint4* st4 = (const uint4*)stage;
-      for (uint32_t q = threadIdx.x; q * 4 < nrec; q += kBlock) out[q] = st4[q];
-      __syncthreads();
-    }
-  }
-  (void)count;
-  if (bad) atomicOr(args.flags, kFlagDomain);
-}
-
-// Wave-level LDS ordering point: every LDS access of the wave issued before
-// it is complete and visible to the wave's other lanes after it.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Pass 1 with one tile of kWaveTile keys per wave (for G <= 16 ranges per
-// row): tickets, prefix sums, key combining and staging are wave-local, so
-// the kernel has no block barriers.  Same record and descriptor format as
-// k_bin with tiles of kWaveTile keys.
-
-// Rows of one wave tile: hash every slot straight-line (no branches, so the
-// slots' Horner chains interleave), take tickets for record-sized weights,
-// prefix the group counts, stage the records in sorted order and copy them
-// out with 16-byte stores.
-template <int PRIME, int MODE, int K, int NP, bool WIDE, int kKpt, typename BA>
-__device__ __forceinline__ void bin_rows_wave(const BA& args, uint32_t tile, uint32_t G, uint32_t lane, uint32_t* hist,
-                                              uint32_t* stage, const uint32_t (&x0)[kKpt], const uint32_t (&x1)[kKpt],
-                                              const int64_t (&wv)[kKpt], const uint32_t (&wpos)[kKpt],
-                                              const uint32_t (&wneg)[kKpt], uint32_t use, uint32_t esc, bool any_esc) {
-  const uint32_t log2r = args.log2r, wbits = 32u - log2r;
-  const uint32_t rmask = (1u << log2r) - 1u;
-  for (uint32_t r = 0; r < args.rows; ++r) {
-    const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
-    uint32_t bk[kKpt], a[kKpt];
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) bucket_sign<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m, bk[j], a[j]);
-    uint32_t rec[kKpt], grp[kKpt], tick[kKpt];
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      grp[j] = bk[j] >> log2r;
-      rec[j] = ((bk[j] & rmask) << wbits) | (a[j] ? wneg[j] : wpos[j]);
-      tick[j] = 0xffffffffu;
-      if ((use >> j) & 1u) tick[j] = atomicAdd(&hist[r * G + grp[j]], 1u);
-    }
-    if (any_esc) {  // weights too large for a record go straight to the table
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j)
-        if ((esc >> j) & 1u) {
-          const int64_t sw = a[j] ? -wv[j] : wv[j];
-          atomicAdd(&args.table[((size_t)r << args.log2m) + bk[j]], (unsigned long long)sw);
-        }
-    }
-    wave_lds_sync();
-    // exclusive prefix over the G <= 16 group counts inside the first 16-lane
-    // DPP row (row_shr 1, 2, 4, 8): lane g holds off[g]
-    const uint32_t cg = lane < G ? hist[r * G + lane] : 0u;
-    uint32_t v = cg;
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);
-    const uint32_t off = v - cg;
-    const uint32_t nrec = __builtin_amdgcn_readlane(v, G - 1);
-    uint32_t* d = args.desc + ((size_t)tile * args.rows + r) * (G + 1);
-    if (lane < G) d[lane] = off;
-    if (lane == G) d[G] = nrec;
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      const uint32_t o = __shfl(off, grp[j] & 15u, 64);
-      if (tick[j] != 0xffffffffu) stage[o + tick[j]] = rec[j];
-    }
-    wave_lds_sync();
-    uint4* out = (uint4*)(args.recs + ((size_t)tile * args.rows + r) * kWaveTile);
-    const uint4* st4 = (const uint4*)stage;
-    for (uint32_t q = lane; q * 4 < nrec; q += 64) out[q] = st4[q];
-    wave_lds_sync();
-  }
-}
-
-// One wave tile of pass 1 (kWaveTile keys of `args`, wave-local LDS `mine`).
-// Returns domain-error bits.
-template <int PRIME, int MODE, int K, typename KeyT, typename WT, bool DEDUP>
-__device__ __forceinline__ uint32_t bin_wave_tile(const BinArgs<KeyT, WT>& args, uint32_t tile, uint32_t lane,
-                                                  unsigned char* mine) {
-  constexpr uint32_t T = kWaveTile;
-  constexpr int kKpt = T / 64;
-  constexpr int NP = MODE == kTwoPoly ? 2 : 1;
-  const uint32_t G = 1u << args.log2g;
-  unsigned long long* skey = (unsigned long long*)mine;
-  long long* swt = (long long*)(mine + T * 8);
-  uint32_t* slots = (uint32_t*)(mine + (DEDUP ? T * 16 : 0));
-  uint32_t* stage = slots;  // reused once the combining table is no longer needed
-  uint32_t* hist = slots + 2 * T;
-  const uint32_t log2r = args.log2r, wbits = 32u - log2r;
-  const uint32_t rmask = (1u << log2r) - 1u;
-  const uint32_t wmask = (1u << wbits) - 1u;
-  const int64_t half = 1ll << (wbits - 1);
-  uint32_t bad = 0;
-  {
-    for (uint32_t i = lane; i < args.rows * G; i += 64) hist[i] = 0;
-    if (DEDUP)
-      for (uint32_t i = lane; i < 2 * T; i += 64) slots[i] = 0;
-    const uint64_t base = (uint64_t)tile * T;
-    uint32_t x0[kKpt], x1[kKpt];
-    int64_t wv[kKpt];
-    bool ok[kKpt];
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      uint64_t i = base + (uint64_t)j * 64 + lane;
-      ok[j] = i < args.n;
-      x0[j] = x1[j] = 0;
-      wv[j] = 0;
-      if (ok[j]) {
-        load_key(args.keys, i, x0[j], x1[j]);
-        wv[j] = load_weight(args.weights, i);
-      }
-    }
-    uint32_t any_hi = 0;
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) any_hi |= x1[j];
-    if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;
-    if constexpr (DEDUP) {
-      // Combine repeated keys of the tile (exact: the sketch is linear).
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j) {
-        const uint32_t idx = j * 64 + lane;
-        skey[idx] = ((unsigned long long)x1[j] << 32) | x0[j];
-        swt[idx] = wv[j];
-      }
-      wave_lds_sync();
-      uint32_t own = 0;
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j) {
-        if (!ok[j]) continue;
-        const uint32_t idx = j * 64 + lane;
-        const unsigned long long key = ((unsigned long long)x1[j] << 32) | x0[j];
-        uint32_t h = dedup_slot(x0[j], x1[j]) & (2 * T - 1);
-        for (uint32_t probe = 0; probe < 2 * T; ++probe) {
-          const uint32_t cur = atomicCAS(&slots[h], 0u, idx + 1);
-          if (cur == 0) {
-            own |= 1u << j;
-            break;
-          }
-          if (skey[cur - 1] == key) {
-            atomicAdd((unsigned long long*)&swt[cur - 1], (unsigned long long)wv[j]);
-            break;
-          }
-          h = (h + 1) & (2 * T - 1);
-        }
-      }
-      wave_lds_sync();
-      unsigned long long ck[kKpt];
-      long long cw[kKpt];
-      uint32_t cnt = 0;
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j) {
-        const uint32_t idx = j * 64 + lane;
-        ck[j] = skey[idx];
-        cw[j] = swt[idx];
-        cnt += (own >> j) & 1u;
-      }
-      uint32_t v = cnt;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += t;
-      }
-      const uint32_t total = __shfl(v, 63, 64);
-      uint32_t pos = v - cnt;
-      wave_lds_sync();
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j)
-        if ((own >> j) & 1u) {
-          skey[pos] = ck[j];
-          swt[pos] = cw[j];
-          ++pos;
-        }
-      wave_lds_sync();
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j) {
-        const uint32_t e = j * 64 + lane;
-        ok[j] = e < total;
-        const unsigned long long key = ok[j] ? skey[e] : 0ull;
-        x0[j] = (uint32_t)key;
-        x1[j] = (uint32_t)(key >> 32);
-        wv[j] = ok[j] ? swt[e] : 0;
-      }
-      wave_lds_sync();
-    }
-    const bool wide = PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0);
-    // per key, independent of the row: record-sized weights (both signs fit
-    // the record field) and the weight's field for both signs
-    uint32_t use = 0, esc = 0;  // bit j: key j goes into a record / is added directly
-    uint32_t wpos[kKpt], wneg[kKpt];
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      const bool small = wv[j] > -half && wv[j] < half;
-      use |= (ok[j] && wv[j] != 0 && small ? 1u : 0u) << j;
-      esc |= (ok[j] && !small ? 1u : 0u) << j;
-      wpos[j] = (uint32_t)wv[j] & wmask;
-      wneg[j] = (uint32_t)(-wv[j]) & wmask;
-    }
-    const bool any_esc = __any(esc != 0);
-    if (wide)
-      bin_rows_wave<PRIME, MODE, K, NP, true, kKpt>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
-    else
-      bin_rows_wave<PRIME, MODE, K, NP, false, kKpt>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
-    }
-  return bad;
-}
-
-template <int PRIME, int MODE, int K, typename KeyT, typename WT, bool DEDUP>
-__global__ __launch_bounds__(kBlock) void k_bin_wave(BinArgs<KeyT, WT> args) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  // wave index made explicitly uniform so the tile loop, the row loop and the
-  // coefficient loads stay scalar
-  const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  unsigned char* mine = smem + (size_t)wave * binw_lds_per_wave<DEDUP>(args.rows, 1u << args.log2g);
-  const uint32_t nw = gridDim.x * (kBlock / 64);
-  uint32_t bad = 0;
-  for (uint32_t tile = blockIdx.x * (kBlock / 64) + wave; tile < args.tiles; tile += nw)
-    bad |= bin_wave_tile<PRIME, MODE, K, KeyT, WT, DEDUP>(args, tile, lane, mine);
-  if (bad) atomicOr(args.flags, kFlagDomain);
-}
 
 // One pass-2 item: records of partition `part` from the tiles of slice
 // `slice`, accumulated in LDS `acc` and added into args.table.
@@ -744,55 +82,6 @@ __global__ __launch_bounds__(kAccBlock) void k_accumulate(AccArgs args) {
   const uint32_t items = (args.rows << args.log2g) * args.slices;
   for (uint32_t item = blockIdx.x; item < items; item += gridDim.x)
     accumulate_item(args, item / args.slices, item % args.slices, acc);
-}
-
-// ---------------------------------------------------------------------------
-// Point query: median over rows of s_j(x) C[j][i_j(x)] (Section 1.3.1).
-// ---------------------------------------------------------------------------
-template <int PRIME, int MODE, int K, typename KeyT>
-__global__ __launch_bounds__(kBlock) void k_query(QueryArgs<KeyT> args) {
-  constexpr int NP = MODE == kTwoPoly ? 2 : 1;
-  uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= args.n) return;
-  uint32_t x0, x1;
-  load_key(args.keys, i, x0, x1);
-  if (PRIME == kPrime61 && (x1 >> 28)) atomicOr(args.flags, kFlagDomain);
-  int64_t vals[kMaxQueryRows];
-  uint32_t rows = args.rows;
-  for (uint32_t r = 0; r < rows; ++r) {
-    uint32_t bk, a;
-    const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
-    if (PRIME == kPrime61 && x1 != 0)
-      bucket_sign<PRIME, MODE, K, true, NP>(c, x0, x1, args.log2m, bk, a);
-    else
-      bucket_sign<PRIME, MODE, K, false, NP>(c, x0, x1, args.log2m, bk, a);
-    int64_t v = args.table[((size_t)r << args.log2m) + bk];
-    v = a ? (int64_t)(0ull - (uint64_t)v) : v;
-    // insertion into the sorted prefix
-    uint32_t p = r;
-    while (p > 0 && vals[p - 1] > v) {
-      vals[p] = vals[p - 1];
-      --p;
-    }
-    vals[p] = v;
-  }
-  args.out[i] = vals[(rows - 1) / 2];
-}
-
-// ---------------------------------------------------------------------------
-// F2 estimate: per (row, slice) 128-bit partial sums of C^2, then one block
-// adds them, checks the int64 range and takes the median over rows.
-// ---------------------------------------------------------------------------
-// A record every lane of the wave reads (a work-list entry), kept in scalar
-// registers.
-template <typename T>
-__device__ __forceinline__ T uniform_load(const T* p) {
-  // all lanes read the same record; copy it through readfirstlane
-  T v = *p;
-  uint32_t* w = reinterpret_cast<uint32_t*>(&v);
-#pragma unroll
-  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
-  return v;
 }
 
 // Sum of squares of one slice of one row (128-bit, with a flag once the
@@ -929,62 +218,6 @@ __global__ void k_fill_zero(unsigned long long* __restrict__ dst, uint64_t n) {
     dst[i] = 0;
 }
 
-// ---------------------------------------------------------------------------
-// Batched update: many independent sketches (same prime, mode and k) in one
-// launch per pass.  Every work item is (sketch, keys), so a wave always hashes
-// with one sketch's coefficients.
-//   k_batch_lds:  items (sketch, key range) of sketches whose table fits LDS
-//   k_batch_bin:  pass 1 over the wave tiles of all segments of a round;
-//                 a wave finds its segment by binary search on tile_begin
-//   k_batch_acc:  pass 2 items (segment, partition, slice)
-// ---------------------------------------------------------------------------
-template <int PRIME, int MODE, int K, typename KeyT, typename WT>
-__global__ __launch_bounds__(kBlock) void k_batch_lds(const BatchSketch* __restrict__ sks,
-                                                      const BatchLdsItem* __restrict__ items, uint32_t nitems) {
-  extern __shared__ unsigned long long lds[];
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const BatchLdsItem item = uniform_load(items + it);
-    const BatchSketch sk = uniform_load(sks + item.sketch);
-    UpdateArgs<KeyT, WT> a{(const KeyT*)sk.keys, (const WT*)sk.weights, sk.n, 0, sk.coeffs, sk.rows, sk.log2m,
-                           sk.table, sk.flags};
-    __syncthreads();  // the previous item's flush has read the LDS table
-    lds_block_update<PRIME, MODE, K, KeyT, WT>(a, item.begin, item.end, lds);
-  }
-}
-
-template <int PRIME, int MODE, int K, typename KeyT, typename WT>
-__global__ __launch_bounds__(kBlock) void k_batch_global(const BatchSketch* __restrict__ sks,
-                                                         const BatchLdsItem* __restrict__ items, uint32_t nitems) {
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const BatchLdsItem item = uniform_load(items + it);
-    const BatchSketch sk = uniform_load(sks + item.sketch);
-    UpdateArgs<KeyT, WT> a{(const KeyT*)sk.keys, (const WT*)sk.weights, sk.n, 0, sk.coeffs, sk.rows, sk.log2m,
-                           sk.table, sk.flags};
-    global_block_update<PRIME, MODE, K, KeyT, WT>(a, item.begin, item.end);
-  }
-}
-
-template <int PRIME, int MODE, int K, typename KeyT, typename WT, bool DEDUP>
-__global__ __launch_bounds__(kBlock) void k_batch_bin(const BatchSegment* __restrict__ segs, uint32_t nsegs,
-                                                      uint32_t total_tiles, uint32_t lds_per_wave) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  unsigned char* mine = smem + (size_t)wave * lds_per_wave;
-  const uint32_t nw = gridDim.x * (kBlock / 64);
-  for (uint32_t gt = blockIdx.x * (kBlock / 64) + wave; gt < total_tiles; gt += nw) {
-    uint32_t lo = 0, hi = nsegs;  // last segment with tile_begin <= gt
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (uniform_load(&segs[mid].tile_begin) <= gt) lo = mid; else hi = mid;
-    }
-    const BatchSegment sg = uniform_load(segs + lo);
-    BinArgs<KeyT, WT> a{(const KeyT*)sg.keys, (const WT*)sg.weights, sg.n, sg.coeffs, sg.rows, sg.log2m, sg.log2g,
-                        sg.log2r, sg.tiles, sg.recs, sg.desc, sg.table, sg.flags};
-    const uint32_t bad = bin_wave_tile<PRIME, MODE, K, KeyT, WT, DEDUP>(a, gt - sg.tile_begin, lane, mine);
-    if (bad) atomicOr(sg.flags, kFlagDomain);
-  }
-}
-
 __global__ __launch_bounds__(kAccBlock) void k_batch_acc(const BatchSegment* __restrict__ segs,
                                                         const BatchAccItem* __restrict__ items, uint32_t nitems) {
   extern __shared__ unsigned long long acc[];
@@ -996,177 +229,65 @@ __global__ __launch_bounds__(kAccBlock) void k_batch_acc(const BatchSegment* __r
   }
 }
 
-template <int PRIME, int MODE, int K, typename KeyT, typename WT>
-static hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t st) {
-  if (b.prepare_only) {  // kernel attributes, set once before any launch or graph capture
-    hipError_t e = hipFuncSetAttribute((const void*)k_batch_lds<PRIME, MODE, K, KeyT, WT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_batch_acc, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(unsigned long long) << kMaxRangeLog2));
-    return e;
-  }
-  if (b.lds_items) {
-    hipLaunchKernelGGL((k_batch_lds<PRIME, MODE, K, KeyT, WT>), dim3(b.lds_blocks), dim3(kBlock), b.lds_bytes, st,
-                       b.sketches, b.lds_item_list, b.lds_items);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (b.glb_items) {
-    hipLaunchKernelGGL((k_batch_global<PRIME, MODE, K, KeyT, WT>), dim3(b.glb_blocks), dim3(kBlock), 0, st,
-                       b.sketches, b.glb_item_list, b.glb_items);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  for (uint32_t r = 0; r < b.rounds; ++r) {
-    const BatchRound& rd = b.round_list[r];
-    if (b.dedup)
-      hipLaunchKernelGGL((k_batch_bin<PRIME, MODE, K, KeyT, WT, true>), dim3(rd.bin_blocks), dim3(kBlock),
-                         b.bin_lds_bytes, st, rd.segs, rd.nsegs, rd.total_tiles, b.bin_lds_per_wave);
-    else
-      hipLaunchKernelGGL((k_batch_bin<PRIME, MODE, K, KeyT, WT, false>), dim3(rd.bin_blocks), dim3(kBlock),
-                         b.bin_lds_bytes, st, rd.segs, rd.nsegs, rd.total_tiles, b.bin_lds_per_wave);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch_acc, dim3(rd.acc_blocks), dim3(kAccBlock), b.acc_lds_bytes, st, rd.segs, rd.acc_items,
-                       rd.nacc);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+hipError_t launch_accumulate(const AccArgs& c, uint32_t blocks, uint32_t lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(k_accumulate, dim3(blocks), dim3(kAccBlock), lds_bytes, st, c);
+  return hipGetLastError();
 }
 
-template <int PRIME, int MODE, int K>
-static hipError_t launch_batch_k(const BatchLaunch& b, hipStream_t st) {
-  if (b.key_bytes == 4 && b.weight_bytes == 4) return launch_batch_t<PRIME, MODE, K, uint32_t, int32_t>(b, st);
-  if (b.key_bytes == 4 && b.weight_bytes == 8) return launch_batch_t<PRIME, MODE, K, uint32_t, int64_t>(b, st);
-  if (b.key_bytes == 8 && b.weight_bytes == 4) return launch_batch_t<PRIME, MODE, K, uint64_t, int32_t>(b, st);
-  return launch_batch_t<PRIME, MODE, K, uint64_t, int64_t>(b, st);
+hipError_t launch_batch_acc(const BatchRound& rd, uint32_t lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_acc, dim3(rd.acc_blocks), dim3(kAccBlock), lds_bytes, st, rd.segs, rd.acc_items, rd.nacc);
+  return hipGetLastError();
 }
 
-template <int PRIME, int MODE>
-static hipError_t launch_batch_m(const BatchLaunch& b, hipStream_t st) {
-  switch (b.k) {
-    case 2: return launch_batch_k<PRIME, MODE, 2>(b, st);
-    case 8: return launch_batch_k<PRIME, MODE, 8>(b, st);
-    default: return launch_batch_k<PRIME, MODE, 4>(b, st);
-  }
+// pass 2 holds up to 2^kMaxRangeLog2 int64 counters in dynamic LDS (above the
+// 64 KiB default)
+void set_accumulate_attribute() {
+  (void)hipFuncSetAttribute((const void*)k_accumulate, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(sizeof(unsigned long long) << kMaxRangeLog2));
+}
+
+hipError_t set_batch_acc_attribute() {
+  return hipFuncSetAttribute((const void*)k_batch_acc, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(sizeof(unsigned long long) << kMaxRangeLog2));
 }
 
 hipError_t launch_batch(const BatchLaunch& b, hipStream_t st) {
   if (b.prime == kPrime61) {
-    if (b.mode == kTwoForOne) return launch_batch_m<kPrime61, kTwoForOne>(b, st);
-    if (b.mode == kTwoForOneMsb) return launch_batch_m<kPrime61, kTwoForOneMsb>(b, st);
-    return launch_batch_m<kPrime61, kTwoPoly>(b, st);
+    if (b.mode == kTwoForOne) return launch_batch_pm<kPrime61, kTwoForOne>(b, st);
+    if (b.mode == kTwoForOneMsb) return launch_batch_pm<kPrime61, kTwoForOneMsb>(b, st);
+    if (b.mode == kArbR) return launch_batch_pm<kPrime61, kArbR>(b, st);
+    return launch_batch_pm<kPrime61, kTwoPoly>(b, st);
   }
-  if (b.mode == kTwoForOne) return launch_batch_m<kPrime89, kTwoForOne>(b, st);
-  if (b.mode == kTwoForOneMsb) return launch_batch_m<kPrime89, kTwoForOneMsb>(b, st);
-  return launch_batch_m<kPrime89, kTwoPoly>(b, st);
-}
-
-// ---------------------------------------------------------------------------
-// launch helpers (host side)
-// ---------------------------------------------------------------------------
-template <int PRIME, int MODE, int K, typename KeyT, typename WT>
-static hipError_t launch_update_t(const UpdatePlan& plan, const UpdateArgs<KeyT, WT>& a, hipStream_t st) {
-  if (plan.variant == kVariantBinned) {
-    BinArgs<KeyT, WT> b{a.keys, a.weights, a.n, a.coeffs, a.rows, a.log2m, plan.log2g, plan.log2r, plan.tiles,
-                        plan.recs, plan.desc, a.table, a.flags};
-    static bool attr_set = false;  // dynamic LDS above 64 KiB needs the kernel attribute
-    if (!attr_set) {
-      (void)hipFuncSetAttribute((const void*)k_accumulate, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(sizeof(unsigned long long) << kMaxRangeLog2));
-      (void)hipFuncSetAttribute((const void*)k_bin<PRIME, MODE, K, KeyT, WT, true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      attr_set = true;
-    }
-    if (plan.wave_tiles) {
-      if (plan.dedup)
-        hipLaunchKernelGGL((k_bin_wave<PRIME, MODE, K, KeyT, WT, true>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, b);
-      else
-        hipLaunchKernelGGL((k_bin_wave<PRIME, MODE, K, KeyT, WT, false>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, b);
-    } else if (plan.dedup) {
-      hipLaunchKernelGGL((k_bin<PRIME, MODE, K, KeyT, WT, true>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, b);
-    } else {
-      hipLaunchKernelGGL((k_bin<PRIME, MODE, K, KeyT, WT, false>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, b);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    AccArgs c{plan.recs, plan.desc, plan.tiles, a.rows, a.log2m, plan.log2g, plan.log2r, plan.acc_slices,
-              plan.wave_tiles ? kWaveTile : kBinTile, a.table};
-    hipLaunchKernelGGL(k_accumulate, dim3(plan.acc_blocks), dim3(kAccBlock), plan.acc_lds_bytes, st, c);
-    return hipGetLastError();
-  }
-  if (plan.variant == kVariantLds) {
-    hipLaunchKernelGGL((k_update_lds<PRIME, MODE, K, KeyT, WT>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, a);
-  } else {
-    hipLaunchKernelGGL((k_update_global<PRIME, MODE, K, KeyT, WT>), dim3(plan.blocks), dim3(kBlock), 0, st, a);
-  }
-  return hipGetLastError();
-}
-
-template <int PRIME, int MODE, int K>
-static hipError_t launch_update_k(const UpdatePlan& plan, const UpdateArgsAny& a, hipStream_t st) {
-  if (a.key_bytes == 4 && a.weight_bytes == 4)
-    return launch_update_t<PRIME, MODE, K, uint32_t, int32_t>(plan, a.as<uint32_t, int32_t>(), st);
-  if (a.key_bytes == 4 && a.weight_bytes == 8)
-    return launch_update_t<PRIME, MODE, K, uint32_t, int64_t>(plan, a.as<uint32_t, int64_t>(), st);
-  if (a.key_bytes == 8 && a.weight_bytes == 4)
-    return launch_update_t<PRIME, MODE, K, uint64_t, int32_t>(plan, a.as<uint64_t, int32_t>(), st);
-  return launch_update_t<PRIME, MODE, K, uint64_t, int64_t>(plan, a.as<uint64_t, int64_t>(), st);
-}
-
-template <int PRIME, int MODE>
-static hipError_t launch_update_m(const UpdatePlan& plan, const UpdateArgsAny& a, hipStream_t st) {
-  switch (a.k) {
-    case 2: return launch_update_k<PRIME, MODE, 2>(plan, a, st);
-    case 8: return launch_update_k<PRIME, MODE, 8>(plan, a, st);
-    default: return launch_update_k<PRIME, MODE, 4>(plan, a, st);
-  }
+  if (b.mode == kTwoForOne) return launch_batch_pm<kPrime89, kTwoForOne>(b, st);
+  if (b.mode == kTwoForOneMsb) return launch_batch_pm<kPrime89, kTwoForOneMsb>(b, st);
+  if (b.mode == kArbR) return launch_batch_pm<kPrime89, kArbR>(b, st);
+  return launch_batch_pm<kPrime89, kTwoPoly>(b, st);
 }
 
 hipError_t launch_update(const UpdatePlan& plan, const UpdateArgsAny& a, hipStream_t st) {
   if (a.prime == kPrime61) {
-    if (a.mode == kTwoForOne) return launch_update_m<kPrime61, kTwoForOne>(plan, a, st);
-    if (a.mode == kTwoForOneMsb) return launch_update_m<kPrime61, kTwoForOneMsb>(plan, a, st);
-    return launch_update_m<kPrime61, kTwoPoly>(plan, a, st);
+    if (a.mode == kTwoForOne) return launch_update_pm<kPrime61, kTwoForOne>(plan, a, st);
+    if (a.mode == kTwoForOneMsb) return launch_update_pm<kPrime61, kTwoForOneMsb>(plan, a, st);
+    if (a.mode == kArbR) return launch_update_pm<kPrime61, kArbR>(plan, a, st);
+    return launch_update_pm<kPrime61, kTwoPoly>(plan, a, st);
   }
-  if (a.mode == kTwoForOne) return launch_update_m<kPrime89, kTwoForOne>(plan, a, st);
-  if (a.mode == kTwoForOneMsb) return launch_update_m<kPrime89, kTwoForOneMsb>(plan, a, st);
-  return launch_update_m<kPrime89, kTwoPoly>(plan, a, st);
-}
-
-template <int PRIME, int MODE, int K, typename KeyT>
-static hipError_t launch_query_t(const QueryArgs<KeyT>& a, hipStream_t st) {
-  uint64_t blocks = (a.n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL((k_query<PRIME, MODE, K, KeyT>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, a);
-  return hipGetLastError();
-}
-
-template <int PRIME, int MODE, int K>
-static hipError_t launch_query_k(const QueryArgsAny& a, hipStream_t st) {
-  if (a.key_bytes == 4) return launch_query_t<PRIME, MODE, K, uint32_t>(a.as<uint32_t>(), st);
-  return launch_query_t<PRIME, MODE, K, uint64_t>(a.as<uint64_t>(), st);
-}
-
-template <int PRIME, int MODE>
-static hipError_t launch_query_m(const QueryArgsAny& a, hipStream_t st) {
-  switch (a.k) {
-    case 2: return launch_query_k<PRIME, MODE, 2>(a, st);
-    case 8: return launch_query_k<PRIME, MODE, 8>(a, st);
-    default: return launch_query_k<PRIME, MODE, 4>(a, st);
-  }
+  if (a.mode == kTwoForOne) return launch_update_pm<kPrime89, kTwoForOne>(plan, a, st);
+  if (a.mode == kTwoForOneMsb) return launch_update_pm<kPrime89, kTwoForOneMsb>(plan, a, st);
+  if (a.mode == kArbR) return launch_update_pm<kPrime89, kArbR>(plan, a, st);
+  return launch_update_pm<kPrime89, kTwoPoly>(plan, a, st);
 }
 
 hipError_t launch_query(const QueryArgsAny& a, hipStream_t st) {
   if (a.prime == kPrime61) {
-    if (a.mode == kTwoForOne) return launch_query_m<kPrime61, kTwoForOne>(a, st);
-    if (a.mode == kTwoForOneMsb) return launch_query_m<kPrime61, kTwoForOneMsb>(a, st);
-    return launch_query_m<kPrime61, kTwoPoly>(a, st);
+    if (a.mode == kTwoForOne) return launch_query_pm<kPrime61, kTwoForOne>(a, st);
+    if (a.mode == kTwoForOneMsb) return launch_query_pm<kPrime61, kTwoForOneMsb>(a, st);
+    if (a.mode == kArbR) return launch_query_pm<kPrime61, kArbR>(a, st);
+    return launch_query_pm<kPrime61, kTwoPoly>(a, st);
   }
-  if (a.mode == kTwoForOne) return launch_query_m<kPrime89, kTwoForOne>(a, st);
-  if (a.mode == kTwoForOneMsb) return launch_query_m<kPrime89, kTwoForOneMsb>(a, st);
-  return launch_query_m<kPrime89, kTwoPoly>(a, st);
+  if (a.mode == kTwoForOne) return launch_query_pm<kPrime89, kTwoForOne>(a, st);
+  if (a.mode == kTwoForOneMsb) return launch_query_pm<kPrime89, kTwoForOneMsb>(a, st);
+  if (a.mode == kArbR) return launch_query_pm<kPrime89, kArbR>(a, st);
+  return launch_query_pm<kPrime89, kTwoPoly>(a, st);
 }
 
 hipError_t launch_estimate(const int64_t* table, uint32_t rows, uint32_t log2m, uint32_t slices, EstPartial* part,

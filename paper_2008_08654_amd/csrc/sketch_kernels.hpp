@@ -14,6 +14,7 @@ constexpr int kPrime64c = 3;
 constexpr int kTwoForOne = 0;
 constexpr int kTwoForOneMsb = 1;
 constexpr int kTwoPoly = 2;
+constexpr int kArbR = 3;  // any number of buckets (Algorithm 8)
 
 constexpr int kBlock = 256;          // 4 wave64s
 constexpr int kKeysPerThread = 4;    // keys held in registers per thread per tile
@@ -219,6 +220,20 @@ struct BatchLaunch {
 };
 hipError_t launch_batch(const BatchLaunch& b, hipStream_t st);
 
+// Launchers per (prime, mode), one pair instantiated per translation unit;
+// launch_update / launch_query / launch_batch dispatch to them.
+template <int PRIME, int MODE>
+hipError_t launch_batch_pm(const BatchLaunch& b, hipStream_t st);
+template <int PRIME, int MODE>
+hipError_t launch_update_pm(const UpdatePlan& plan, const UpdateArgsAny& a, hipStream_t st);
+template <int PRIME, int MODE>
+hipError_t launch_query_pm(const QueryArgsAny& a, hipStream_t st);
+// pass-2 launches and LDS attributes shared by every instantiation
+hipError_t launch_accumulate(const AccArgs& c, uint32_t blocks, uint32_t lds_bytes, hipStream_t st);
+hipError_t launch_batch_acc(const BatchRound& rd, uint32_t lds_bytes, hipStream_t st);
+void set_accumulate_attribute();
+hipError_t set_batch_acc_attribute();
+
 // LDS bytes of one wave of the wave-tile pass 1:
 //   [combining: keys u64[T] | weights i64[T]] | slots u32[2T] (records are
 //   staged there) | counters u32[rows*G], padded to 16 bytes.
@@ -242,6 +257,8 @@ hipError_t launch_add_tables(unsigned long long* dst, const unsigned long long* 
 hipError_t launch_fill_zero(unsigned long long* dst, uint64_t n, hipStream_t st);
 
 // quotient / remainder
+hipError_t launch_bucket_map(int prime, bool fast, const uint64_t* v, uint64_t n, uint32_t r, uint32_t* out,
+                             uint32_t* flags, uint32_t cus, hipStream_t st);
 hipError_t launch_divmod(int prime, bool naive, const uint64_t* x, uint64_t n, uint64_t* quot, uint64_t* rem,
                          uint32_t* flags, hipStream_t st);
 
