@@ -37,13 +37,16 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.32 T 32-bit lane-ops/s (full-
 HBM_PEAK_GBS = 8000.0
 METRIC = "Gkeys/s into Count Sketch (p=2^61-1, 4-universal) + % of binding roofline"
 
-# Algorithmic 32-bit VALU operations per key and row, one straight-line sequence
-# per configuration, fixed before tuning (derivation in the design notes):
-#   p61, key < 2^32, k=4: 3 Horner steps x 9 + final 4 + split/sign/address 5 = 36
-#   p61 two-polynomial: 2 x (27 + 4) + 5 = 67
-#   p89, 64-bit key, k=4: 3 steps x 24 (6 mad_u64_u32 + 10 carry adds + 3 funnel
-#     shifts + 5 fold adds) + final 10 + split/sign/address 5 = 87
-OPS_PER_KEY_ROW = {("p61", 0): 36, ("p61", 2): 67, ("p89", 0): 87}
+# Algorithmic 32-bit VALU operations per key and row: the VALU instructions
+# (register moves not counted, so a lower bound) of the compiled straight-line
+# hash + final reduction + split of one row on gfx950, plus 2 per row for the
+# signed-weight select and the counter address / record.  Counts taken from the
+# gfx950 assembly of bucket_sign (profiles/valu_ops_per_key_row.md):
+#   p61, key < 2^32, two-for-one: 3 Horner steps x 6 + final reduction 4 + split = 22, + 2 = 24
+#   p61 two polynomials: 41 + 2 = 43
+#   p61 any bucket count (Algorithm 8): 25 + 2 = 27
+#   p89, 64-bit keys, two-for-one: 60 + 2 = 62
+OPS_PER_KEY_ROW = {("p61", 0): 24, ("p61", 2): 43, ("p89", 0): 62, ("p61", 3): 27}
 OPS_PER_KEY = 3  # weight negation (2) and domain check (1)
 
 SKETCH_WORKLOADS = {
@@ -56,12 +59,21 @@ SKETCH_WORKLOADS = {
     "small_table_u32": dict(n=1 << 28, rows=5, log2m=10, mode=0, prime="p61", keys="u32", kbytes=4, wbytes=8,
                             seed=1001, desc="2^28 uint32 keys uniform, int64 weights = 1, p=2^61-1, t=5, m=2^10 "
                                             "(table in LDS), two-for-one"),
+    "single_stream_zipf_arb_r": dict(n=1 << 28, rows=9, log2m=16, buckets=50000, mode=3, prime="p61", keys="zipf",
+                                     kbytes=8, wbytes=4, seed=1002,
+                                     desc="as single_stream_zipf with r = 50000 buckets per row (Algorithm 8, any "
+                                          "bucket count; rows padded to 2^16)"),
     "small_table_u32_two_poly": dict(n=1 << 28, rows=5, log2m=10, mode=2, prime="p61", keys="u32", kbytes=4,
                                      wbytes=8, seed=1001, desc="as small_table_u32 with two independent polynomials "
                                                                "per row (bucket, sign): the hashing-bound comparison"),
     "p89_uniform": dict(n=1 << 26, rows=5, log2m=20, mode=0, prime="p89", keys="u64", kbytes=8, wbytes=8,
                         seed=1003, desc="2^26 uint64 keys uniform, int64 weights = 1, p=2^89-1, t=5, m=2^20, "
                                         "two-for-one"),
+}
+MAP_WORKLOADS = {
+    "bucket_map_p61": dict(prime=1, p=(1 << 61) - 1, limbs=1, n=1 << 28, r=1000003),
+    "bucket_map_p89": dict(prime=2, p=(1 << 89) - 1, limbs=2, n=1 << 28, r=1000003),
+    "bucket_map_p64_59": dict(prime=3, p=(1 << 64) - 59, limbs=1, n=1 << 28, r=1000003),
 }
 DIVMOD_WORKLOADS = {
     "divmod_p61": dict(prime=1, p=(1 << 61) - 1, limbs=2, qlimbs=1, n=1 << 28),
@@ -119,7 +131,7 @@ def cpu_baseline_sketch(keys_dev, w_dev, wl, budget_s=15.0):
     prefix of the same stream, one thread per row."""
     import numpy as np
     import oracle as O
-    rows, m, mode = wl["rows"], 1 << wl["log2m"], wl["mode"]
+    rows, m, mode = wl["rows"], wl.get("buckets", 1 << wl["log2m"]), wl["mode"]
     prime = O.PRIME_P61 if wl["prime"] == "p61" else O.PRIME_P89
     threads = min(rows, os.cpu_count() or 1)
     coeffs = O.coeffs_from_seed(prime, rows, mode, wl["seed"])
@@ -153,7 +165,7 @@ def run_sketch(args, wl):
     import workloads as W
 
     n = args.n or wl["n"]
-    rows, m, mode = wl["rows"], 1 << wl["log2m"], wl["mode"]
+    rows, m, mode = wl["rows"], wl.get("buckets", 1 << wl["log2m"]), wl["mode"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t_gen = time.perf_counter()
@@ -433,6 +445,63 @@ def run_served(args):
     return out
 
 
+def run_bucket_map(args, wl):
+    """Most uniform maps of 2^28 hash values uniform in [p] to r = 1000003 buckets: the exact
+    floor(v r / p) (Algorithms 4 or 5-6 on the product) and, for Mersenne primes, ((v+1) r) >> b."""
+    import numpy as np
+    import torch
+    import paper_2008_08654_amd as M
+    import workloads as W
+
+    n = args.n or wl["n"]
+    dev = torch.device("cuda:0")
+    v = W.below_limbs(wl["p"], wl["limbs"], 0x2008086544, n, device=dev)
+    v = v.reshape(-1) if wl["limbs"] == 1 else v.contiguous()
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def timed(method):
+        for _ in range(args.warmup):
+            M.mersenne_bucket_map(wl["prime"], v, wl["r"], out, method=method)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for a, b in ev:
+            a.record()
+            M.mersenne_bucket_map(wl["prime"], v, wl["r"], out, method=method)
+            b.record()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, sum(a.elapsed_time(b) for a, b in ev) / len(ev)
+
+    elapsed, k_ms = timed(M.CS_MAP_EXACT)
+    M.mersenne_status()
+    fast_ms = None
+    if wl["prime"] != M.CS_P64_59:
+        _, fast_ms = timed(M.CS_MAP_MERSENNE)
+        M.mersenne_status()
+    bytes_per = 8 * wl["limbs"] + 4
+    gbs = bytes_per * n / (k_ms * 1e-3) / 1e9
+    out_d = {"metric": "G values/s most uniform map of hash values to r buckets (exact floor(v r / p)) + % of HBM roofline",
+             "value": round(n * args.steps / elapsed / 1e9, 3), "unit": "Gvalues/s", "n_gpus": 1,
+             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
+             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+             "config": {"workload": args.workload, "values": n, "r": wl["r"], "limbs_in": wl["limbs"],
+                        "mersenne_map_kernel_ms": None if fast_ms is None else round(fast_ms, 4)},
+             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, n),
+                          "algorithmic_bytes_per_launch": bytes_per * n, "kernel": "k_bucket_map",
+                          "kernel_avg_ms": round(k_ms, 4), "algorithmic_bytes_per_value": bytes_per}}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        nn = 1 << 22
+        vh = v[:nn].cpu().numpy().view(np.uint64)
+        t0 = time.perf_counter()
+        O.bucket_map_exact(wl["p"], vh, wl["r"])
+        dt = time.perf_counter() - t0
+        out_d["cpu_baseline"] = {"value": round(nn / dt / 1e9, 6), "unit": "Gvalues/s", "cores": 1, "kind": "oracle",
+                                 "sample": f"first {nn} values, {dt:.2f} s, one thread"}
+    return out_d
+
+
 def run_divmod(args, wl):
     import numpy as np
     import torch
@@ -498,7 +567,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single_stream_zipf",
-                    choices=sorted(SKETCH_WORKLOADS) + sorted(DIVMOD_WORKLOADS) + ["batched", "served"])
+                    choices=sorted(SKETCH_WORKLOADS) + sorted(DIVMOD_WORKLOADS) + sorted(MAP_WORKLOADS)
+                    + ["batched", "served"])
     ap.add_argument("--n", type=int, default=None, help="override the number of keys / values")
     ap.add_argument("--path", type=int, default=0, help="force an update path (1 LDS, 2 global, 3 binned)")
     ap.add_argument("--direct-fraction", type=float, default=0.0,
@@ -523,6 +593,8 @@ def main():
         out = run_batched(args)
     elif args.workload == "served":
         out = run_served(args)
+    elif args.workload in MAP_WORKLOADS:
+        out = run_bucket_map(args, MAP_WORKLOADS[args.workload])
     elif args.workload in SKETCH_WORKLOADS:
         out = run_sketch(args, SKETCH_WORKLOADS[args.workload])
     else:
