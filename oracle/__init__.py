@@ -295,6 +295,49 @@ def bucket_map_mersenne(b: int, v, r: int) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
+# wide quotient and remainder (Section 4's experiment): x of 2b bits divided by
+# p = 2^b - c, b a multiple of 32.  Values are "limb planes": a uint32 array of
+# shape (limbs, n) whose row j holds limb j (bits 32j..32j+31) of every value.
+# The oracle is the plain definition, Python's integer divmod per value.
+# --------------------------------------------------------------------------
+def planes_to_ints(planes) -> list[int]:
+    planes = np.asarray(planes, dtype=np.uint32)
+    out = [0] * planes.shape[1]
+    for j in range(planes.shape[0] - 1, -1, -1):
+        row = planes[j].tolist()
+        out = [(o << 32) | v for o, v in zip(out, row)]
+    return out
+
+
+def ints_to_planes(vals, limbs: int) -> np.ndarray:
+    out = np.zeros((limbs, len(vals)), dtype=np.uint32)
+    for i, v in enumerate(vals):
+        if v < 0 or v >> (32 * limbs):
+            raise ValueError("value does not fit the limbs")
+        for j in range(limbs):
+            out[j, i] = (v >> (32 * j)) & 0xFFFFFFFF
+    return out
+
+
+def divmod_wide(b: int, c: int, x_planes) -> tuple[np.ndarray, np.ndarray]:
+    """floor(x / p) and x mod p for p = 2^b - c and every 2b-bit x (planes of 2b/32 limbs).
+    Returns (quotient planes with b/32 + 1 limbs, remainder planes with b/32 limbs)."""
+    if b % 32 or b <= 0 or not 0 < c < (1 << b) - 1:
+        raise ValueError("b must be a positive multiple of 32 and 0 < c < 2^b - 1")
+    w = b // 32
+    x_planes = np.asarray(x_planes, dtype=np.uint32)
+    if x_planes.shape[0] != 2 * w:
+        raise ValueError("x needs 2b/32 limbs")
+    p = (1 << b) - c
+    qs, rs = [], []
+    for x in planes_to_ints(x_planes):
+        q, r = divmod(x, p)
+        qs.append(q)
+        rs.append(r)
+    return ints_to_planes(qs, w + 1), ints_to_planes(rs, w)
+
+
+# --------------------------------------------------------------------------
 # exhaustive enumeration over Z_p^k (tiny primes)
 # --------------------------------------------------------------------------
 def enum_hash(p: int, k: int, keys) -> np.ndarray:

@@ -593,3 +593,43 @@ def test_arb_r_invalid_counts_and_linearity():
     O.cs_update(O.PRIME_P61, O.ARB_R, 3, 1000, coeffs, keys[150:], w[150:], table=part)
     assert np.array_equal(whole, part)
     assert int(np.abs(whole).sum()) > 0
+
+
+# ---------------------------------------------------------------------------
+# wide quotient and remainder (the b-sweep of Section 5's division experiment)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("b", [32, 64, 128, 256, 512, 1024])
+def test_wide_divmod_closed_forms(b):
+    """p = 2^b - 1: 2^(2b) - 1 = p (p + 2) gives q = p + 2 = 2^b + 1, r = 0; p^2 - 1 gives
+    q = p - 1, r = p - 1; k p + j gives (k, j); 0 gives (0, 0)."""
+    p = (1 << b) - 1
+    vals = [(1 << (2 * b)) - 1, p * p - 1, 0, p, p - 1, 5 * p + 3, (p - 1) * p + (p - 1)]
+    want = [(p + 2, 0), (p - 1, p - 1), (0, 0), (1, 0), (0, p - 1), (5, 3), (p - 1, p - 1)]
+    q, r = O.divmod_wide(b, 1, O.ints_to_planes(vals, 2 * b // 32))
+    got = list(zip(O.planes_to_ints(q), O.planes_to_ints(r)))
+    assert got == want
+
+
+def test_wide_divmod_matches_128_bit_oracle():
+    """b = 64, c = 59 (p = 2^64 - 59): the same values through the C oracle's 128-bit
+    division (an independent implementation)."""
+    rng = np.random.default_rng(3)
+    p = (1 << 64) - 59
+    vals = [int(v) for v in rng.integers(0, 2 ** 63, 200, dtype=np.uint64)]
+    vals = [(v * p + (v % p)) % (p << 64) for v in vals] + [0, p - 1, p, (p << 64) - 1]
+    x = np.array([[v & (2 ** 64 - 1), v >> 64] for v in vals], dtype=np.uint64)
+    q1, r1 = O.divmod_batch(O.PRIME_P64_59, x)
+    q2, r2 = O.divmod_wide(64, 59, O.ints_to_planes(vals, 4))
+    assert O.planes_to_ints(q2) == [int(v) for v in q1]
+    assert O.planes_to_ints(r2) == [int(v) for v in r1]
+
+
+def test_wide_planes_round_trip_and_arguments():
+    vals = [0, 1, (1 << 256) - 1, 12345678901234567890123456789]
+    assert O.planes_to_ints(O.ints_to_planes(vals, 8)) == vals
+    with pytest.raises(ValueError):
+        O.ints_to_planes([1 << 256], 8)
+    with pytest.raises(ValueError):
+        O.divmod_wide(48, 1, np.zeros((3, 1), dtype=np.uint32))
+    with pytest.raises(ValueError):
+        O.divmod_wide(64, 1, np.zeros((3, 1), dtype=np.uint32))
