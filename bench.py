@@ -502,6 +502,68 @@ def run_bucket_map(args, wl):
     return out_d
 
 
+def run_divmod_bsweep(args):
+    """The paper's division experiment on the GPU: 10^7 divisions of uniform 2b-bit numbers
+    by p = 2^b - 1 for b = 32 .. 1024, Algorithm 5 (+ 6) against the Crandall-Chung-Hasan
+    algorithm (Algorithm 10); limb-plane layout."""
+    import numpy as np
+    import torch
+    import paper_2008_08654_amd as M
+    import workloads as W
+
+    n = args.n or 10 ** 7
+    dev = torch.device("cuda:0")
+    sweep = {}
+    for b in (32, 64, 128, 256, 512, 1024):
+        w = b // 32
+        x = W.uniform_u32(0x2008086545 + b, 2 * w * n, device=dev).to(torch.int32).reshape(2 * w, n)
+        q = torch.empty((w + 1, n), dtype=torch.int32, device=dev)
+        r = torch.empty((w, n), dtype=torch.int32, device=dev)
+        res = {}
+        for name, method in (("alg5", M.CS_WIDE_ALG5), ("cch", M.CS_WIDE_CCH)):
+            for _ in range(args.warmup):
+                M.mersenne_divmod_wide(b, 1, x, q, r, method=method)
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+            for a, e in ev:
+                a.record()
+                M.mersenne_divmod_wide(b, 1, x, q, r, method=method)
+                e.record()
+            torch.cuda.synchronize()
+            res[name] = sum(a.elapsed_time(e) for a, e in ev) / len(ev)
+        bytes_per = 4 * (2 * w + (w + 1) + w)
+        sweep[b] = {"alg5_ms_per_1e7": round(res["alg5"] * 1e7 / n, 4), "cch_ms_per_1e7": round(res["cch"] * 1e7 / n, 4),
+                    "cch_over_alg5": round(res["cch"] / res["alg5"], 2),
+                    "alg5_gb_per_s": round(bytes_per * n / (res["alg5"] * 1e-3) / 1e9, 1)}
+        _log(f"divmod_bsweep: b = {b}: {sweep[b]}")
+        del x, q, r
+    top = sweep[1024]
+    k_ms = top["alg5_ms_per_1e7"] * n / 1e7
+    bytes_per = 4 * (2 * 32 + 33 + 32)
+    gbs = bytes_per * n / (k_ms * 1e-3) / 1e9
+    out = {"metric": "G divisions/s of 2048-bit numbers by 2^1024 - 1 (Algorithm 5), with the b = 32..1024 sweep "
+                     "against the Crandall-Chung-Hasan algorithm",
+           "value": round(n / (k_ms * 1e-3) / 1e9, 3), "unit": "Gdivisions/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(k_ms, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32 limbs", "data": "synthetic",
+           "config": {"workload": "divmod_bsweep", "divisions": n, "c": 1, "layout": "limb planes",
+                      "sweep": {str(k): v for k, v in sweep.items()}},
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic("divmod_bsweep", n),
+                        "algorithmic_bytes_per_launch": bytes_per * n, "kernel": "k_wide_alg5<32>",
+                        "kernel_avg_ms": round(k_ms, 4), "algorithmic_bytes_per_value": bytes_per}}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        nn = 20000
+        xh = W.uniform_u32(0x2008086545 + 1024, 64 * nn).numpy().astype(np.uint32).reshape(64, nn)
+        t0 = time.perf_counter()
+        O.divmod_wide(1024, 1, xh)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(nn / dt / 1e9, 9), "unit": "Gdivisions/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{nn} divisions at b = 1024 (Python integer divmod), {dt:.2f} s"}
+    return out
+
+
 def run_divmod(args, wl):
     import numpy as np
     import torch
@@ -568,7 +630,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single_stream_zipf",
                     choices=sorted(SKETCH_WORKLOADS) + sorted(DIVMOD_WORKLOADS) + sorted(MAP_WORKLOADS)
-                    + ["batched", "served"])
+                    + ["batched", "served", "divmod_bsweep"])
     ap.add_argument("--n", type=int, default=None, help="override the number of keys / values")
     ap.add_argument("--path", type=int, default=0, help="force an update path (1 LDS, 2 global, 3 binned)")
     ap.add_argument("--direct-fraction", type=float, default=0.0,
@@ -593,6 +655,8 @@ def main():
         out = run_batched(args)
     elif args.workload == "served":
         out = run_served(args)
+    elif args.workload == "divmod_bsweep":
+        out = run_divmod_bsweep(args)
     elif args.workload in MAP_WORKLOADS:
         out = run_bucket_map(args, MAP_WORKLOADS[args.workload])
     elif args.workload in SKETCH_WORKLOADS:

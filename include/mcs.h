@@ -195,6 +195,21 @@ enum { CS_MAP_EXACT = 0, CS_MAP_MERSENNE = 1 };
 cs_status mersenne_bucket_map(cs_prime prime, int method, const uint64_t* v, uint64_t n, uint64_t r, uint32_t* out,
                               hipStream_t stream);
 
+/* Wide quotient and remainder (the division experiment of Section 5): every x of
+ * 2b bits divided by p = 2^b - c, for b in {32, 64, 128, 256, 512, 1024} and
+ * 1 <= c < min(2^31, 2^(b/2)).
+ *   CS_WIDE_ALG5: Algorithm 5 with m = ceil(2b / (b - ceil(log2 c))) steps (2 for
+ *                 c = 1; Theorem simple-div), then Algorithm 6
+ *   CS_WIDE_CCH:  the Crandall-Chung-Hasan algorithm (Algorithm 10), the paper's
+ *                 comparator
+ * Values are limb planes of uint32: limb j (bits 32j..32j+31) of value i at
+ * x[j*n + i].  x: device, 2b/32 planes; quot: device, b/32 + 1 planes; rem:
+ * device, b/32 planes; quot or rem may be NULL.  Every x < 2^(2b) is in the
+ * domain.  Enqueued on `stream`. */
+enum { CS_WIDE_ALG5 = 0, CS_WIDE_CCH = 1 };
+cs_status mersenne_divmod_wide(uint32_t b, uint32_t c, int method, const uint32_t* x, uint64_t n, uint32_t* quot,
+                               uint32_t* rem, hipStream_t stream);
+
 /* Synchronises `stream` and returns (and clears) the domain flag of the
  * quotient/remainder calls on the current device. */
 cs_status mersenne_status(hipStream_t stream);

@@ -23,6 +23,7 @@ CS_OK, CS_EINVAL, CS_ENOMEM, CS_EDOMAIN, CS_EOVERFLOW, CS_EDEVICE, CS_EBUSY = 0,
 CS_P61, CS_P89, CS_P64_59 = 1, 2, 3
 CS_TWO_FOR_ONE, CS_TWO_FOR_ONE_MSB, CS_TWO_POLY, CS_ARB_R = 0, 1, 2, 3
 CS_MAP_EXACT, CS_MAP_MERSENNE = 0, 1
+CS_WIDE_ALG5, CS_WIDE_CCH = 0, 1
 CS_U32, CS_U64, CS_I32, CS_I64 = 0, 1, 2, 3
 CS_PATH_AUTO, CS_PATH_LDS, CS_PATH_GLOBAL, CS_PATH_BINNED, CS_PATH_BINNED_NOCOMBINE = 0, 1, 2, 3, 4
 
@@ -67,6 +68,7 @@ def lib() -> ctypes.CDLL:
             "mersenne_divmod_naive": [i32, P, u64, P, P, P],
             "mersenne_status": [P],
             "mersenne_bucket_map": [i32, i32, P, u64, u64, P, P],
+            "mersenne_divmod_wide": [u32, u32, i32, P, u64, P, P, P],
             "cs_batch_create": [P, u32, i32, i32, P, P],
             "cs_batch_update": [P, P],
             "cs_batch_autotune": [P, P, P],
@@ -446,6 +448,16 @@ def mersenne_bucket_map(prime: int, v, r: int, out, method: int = CS_MAP_EXACT, 
     """Buckets in [r] of hash values v < p (uint64 tensor of shape (n,), or (n, 2) limbs for
     2^89 - 1) into out (int32 tensor of n uint32 bit patterns)."""
     _check(lib().mersenne_bucket_map(prime, method, _dev_ptr(v), v.shape[0], r, _dev_ptr(out), _stream(stream)))
+
+
+def mersenne_divmod_wide(b: int, c: int, x, quot=None, rem=None, method: int = CS_WIDE_ALG5, stream=None):
+    """Quotient and remainder of 2b-bit values by 2^b - c.  x: int32 tensor of limb planes,
+    shape (2b/32, n); quot: (b/32 + 1, n); rem: (b/32, n) (uint32 bit patterns)."""
+    w = b // 32
+    if x.shape[0] != 2 * w or (quot is not None and quot.shape[0] != w + 1) or (rem is not None and rem.shape[0] != w):
+        raise ValueError("limb-plane shapes do not match b")
+    _check(lib().mersenne_divmod_wide(b, c, method, _dev_ptr(x), x.shape[1], _dev_ptr(quot) if quot is not None else None,
+                                      _dev_ptr(rem) if rem is not None else None, _stream(stream)))
 
 
 def mersenne_status(stream=None):

@@ -612,6 +612,25 @@ extern "C" cs_status mersenne_bucket_map(cs_prime prime, int method, const uint6
   return CS_OK;
 }
 
+extern "C" cs_status mersenne_divmod_wide(uint32_t b, uint32_t c, int method, const uint32_t* x, uint64_t n,
+                                          uint32_t* quot, uint32_t* rem, hipStream_t stream) {
+  if (b != 32 && b != 64 && b != 128 && b != 256 && b != 512 && b != 1024)
+    return fail(CS_EINVAL, "b must be 32, 64, 128, 256, 512 or 1024");
+  if (c == 0 || c >= (1u << 31)) return fail(CS_EINVAL, "c must be in [1, 2^31)");
+  if (method != CS_WIDE_ALG5 && method != CS_WIDE_CCH) return fail(CS_EINVAL, "unknown method %d", method);
+  if (n == 0) return CS_OK;
+  if (!x) return fail(CS_EINVAL, "x is NULL");
+  if (!quot && !rem) return fail(CS_EINVAL, "quot and rem are both NULL");
+  // Algorithm 5's step count: (2^b / c)^m >= 2^(2b) > x holds once m (b - ceil(log2 c)) >= 2b
+  uint32_t lc = 0;
+  while ((1ull << lc) < c) ++lc;
+  if (2 * lc >= b) return fail(CS_EINVAL, "c must be below 2^(b/2)");
+  const uint32_t m = (2 * b + (b - lc) - 1) / (b - lc);
+  hipError_t e = launch_wide_divmod(b, c, m, method, x, n, quot, rem, stream);
+  if (e != hipSuccess) return hip_fail(e, "wide divmod launch");
+  return CS_OK;
+}
+
 extern "C" cs_status mersenne_status(hipStream_t stream) {
   uint32_t* flags = divmod_flags();
   if (!flags) return fail(CS_ENOMEM, "flag allocation");

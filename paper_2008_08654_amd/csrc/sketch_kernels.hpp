@@ -257,6 +257,8 @@ hipError_t launch_add_tables(unsigned long long* dst, const unsigned long long* 
 hipError_t launch_fill_zero(unsigned long long* dst, uint64_t n, hipStream_t st);
 
 // quotient / remainder
+hipError_t launch_wide_divmod(uint32_t b, uint32_t c, uint32_t m, int method, const uint32_t* x, uint64_t n,
+                              uint32_t* quot, uint32_t* rem, hipStream_t st);
 hipError_t launch_bucket_map(int prime, bool fast, const uint64_t* v, uint64_t n, uint32_t r, uint32_t* out,
                              uint32_t* flags, uint32_t cus, hipStream_t st);
 hipError_t launch_divmod(int prime, bool naive, const uint64_t* x, uint64_t n, uint64_t* quot, uint64_t* rem,
