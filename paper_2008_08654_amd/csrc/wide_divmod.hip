@@ -15,8 +15,8 @@
 
 namespace mcs {
 
-// z c + a for the limbs of z (W + 1 limbs) times the 32-bit c: limb j of the
-// product, with its running carry `mc`.
+// Limb j of z c for a multi-limb z and a 32-bit c, with the product's running
+// carry `mc` (for c = 1 the limb itself).
 template <bool C1>
 __device__ __forceinline__ uint32_t zc_limb(uint32_t zj, uint32_t c, uint64_t& mc) {
   if (C1) return zj;
@@ -26,18 +26,23 @@ __device__ __forceinline__ uint32_t zc_limb(uint32_t zj, uint32_t c, uint64_t& m
 }
 
 template <int W, bool C1>
-__global__ __launch_bounds__(kBlock) void k_wide_alg5(const uint32_t* __restrict__ x, uint64_t n, uint32_t c,
+__global__ __launch_bounds__(kBlock, 2) void k_wide_alg5(const uint32_t* __restrict__ x, uint64_t n, uint32_t c,
                                                       uint32_t m, uint32_t* __restrict__ quot,
                                                       uint32_t* __restrict__ rem) {
   const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   uint32_t vp[2 * W + 1], z[W + 1];
+  // all limbs are loaded before the carry chain uses any, so the loads are in
+  // flight together
+  const uint32_t* px = x + i;
+#pragma unroll
+  for (int j = 0; j < 2 * W; ++j, px += n) vp[j] = *px;
   // v' = v + c (one more limb for the carry)
-  uint64_t s = (uint64_t)x[i] + c;
+  uint64_t s = (uint64_t)vp[0] + c;
   vp[0] = (uint32_t)s;
 #pragma unroll
   for (int j = 1; j < 2 * W; ++j) {
-    s = (uint64_t)x[(size_t)j * n + i] + (s >> 32);
+    s = (uint64_t)vp[j] + (s >> 32);
     vp[j] = (uint32_t)s;
   }
   vp[2 * W] = (uint32_t)(s >> 32);
@@ -77,18 +82,18 @@ __global__ __launch_bounds__(kBlock) void k_wide_alg5(const uint32_t* __restrict
   }
 }
 
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_wide_cch(const uint32_t* __restrict__ x, uint64_t n, uint32_t c,
+template <int W, bool C1>
+__global__ __launch_bounds__(kBlock, 2) void k_wide_cch(const uint32_t* __restrict__ x, uint64_t n, uint32_t c,
                                                      uint32_t* __restrict__ quot, uint32_t* __restrict__ rem) {
   const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   // q = q_0 = x >> b, r = r_0 = x mod 2^b (one spare limb each for the sums)
   uint32_t q[W + 1], r[W + 1];
+  const uint32_t* px = x + i;
 #pragma unroll
-  for (int j = 0; j < W; ++j) {
-    r[j] = x[(size_t)j * n + i];
-    q[j] = x[(size_t)(W + j) * n + i];
-  }
+  for (int j = 0; j < W; ++j, px += n) r[j] = *px;
+#pragma unroll
+  for (int j = 0; j < W; ++j, px += n) q[j] = *px;
   q[W] = r[W] = 0;
   // first pass of the loop, t = q_0 c: r += t mod 2^b, q_1 = t >> b (one limb)
   uint32_t any = 0;
@@ -99,9 +104,8 @@ __global__ __launch_bounds__(kBlock) void k_wide_cch(const uint32_t* __restrict_
     uint64_t mc = 0, cr = 0;
 #pragma unroll
     for (int j = 0; j < W; ++j) {
-      const uint64_t p = (uint64_t)q[j] * c + mc;
-      mc = p >> 32;
-      const uint64_t a = (uint64_t)r[j] + (uint32_t)p + cr;
+      const uint32_t lo = zc_limb<C1>(q[j], c, mc);
+      const uint64_t a = (uint64_t)r[j] + lo + cr;
       r[j] = (uint32_t)a;
       cr = a >> 32;
     }
@@ -173,8 +177,10 @@ template <int W>
 static hipError_t launch_wide_w(int method, uint32_t c, uint32_t m, const uint32_t* x, uint64_t n, uint32_t* quot,
                                 uint32_t* rem, hipStream_t st) {
   const uint32_t blocks = (uint32_t)((n + kBlock - 1) / kBlock);
-  if (method == 1)
-    hipLaunchKernelGGL((k_wide_cch<W>), dim3(blocks), dim3(kBlock), 0, st, x, n, c, quot, rem);
+  if (method == 1 && c == 1)
+    hipLaunchKernelGGL((k_wide_cch<W, true>), dim3(blocks), dim3(kBlock), 0, st, x, n, c, quot, rem);
+  else if (method == 1)
+    hipLaunchKernelGGL((k_wide_cch<W, false>), dim3(blocks), dim3(kBlock), 0, st, x, n, c, quot, rem);
   else if (c == 1)
     hipLaunchKernelGGL((k_wide_alg5<W, true>), dim3(blocks), dim3(kBlock), 0, st, x, n, c, m, quot, rem);
   else
