@@ -502,29 +502,35 @@ __device__ __forceinline__ void wave_lds_sync() {
 // slots' Horner chains interleave), take tickets for record-sized weights,
 // prefix the group counts, stage the records in sorted order and copy them
 // out with 16-byte stores.
-template <int PRIME, int MODE, int K, int NP, bool WIDE, int kKpt, typename BA>
+template <int PRIME, int MODE, int K, int NP, bool WIDE, int kKpt, int kUse, typename BA>
 __device__ __forceinline__ void bin_rows_wave(const BA& args, uint32_t tile, uint32_t G, uint32_t lane, uint32_t* hist,
                                               uint32_t* stage, const uint32_t (&x0)[kKpt], const uint32_t (&x1)[kKpt],
                                               const int64_t (&wv)[kKpt], const uint32_t (&wpos)[kKpt],
                                               const uint32_t (&wneg)[kKpt], uint32_t use, uint32_t esc, bool any_esc) {
+  static_assert(kUse <= kKpt, "more slots than the tile holds");
   const uint32_t log2r = args.log2r, wbits = 32u - log2r;
   const uint32_t rmask = (1u << log2r) - 1u;
+  // Lanes without a record in a slot take their ticket from a counter of their
+  // own and stage into a word of their own (words kWaveTile.. of the staging
+  // area, past every record), so the slots need no branches.
+  uint32_t* const stage_sink = stage + kWaveTile + lane;
+  uint32_t* const ticket_sink = stage + kWaveTile + 64 + lane;
   for (uint32_t r = 0; r < args.rows; ++r) {
     const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
-    uint32_t bk[kKpt], a[kKpt];
+    uint32_t bk[kUse], a[kUse];
 #pragma unroll
-    for (int j = 0; j < kKpt; ++j) bucket_sign<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m, bk[j], a[j]);
-    uint32_t rec[kKpt], grp[kKpt], tick[kKpt];
+    for (int j = 0; j < kUse; ++j) bucket_sign<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m, bk[j], a[j]);
+    uint32_t rec[kUse], grp[kUse], tick[kUse];
 #pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
+    for (int j = 0; j < kUse; ++j) {
       grp[j] = bk[j] >> log2r;
       rec[j] = ((bk[j] & rmask) << wbits) | (a[j] ? wneg[j] : wpos[j]);
-      tick[j] = 0xffffffffu;
-      if ((use >> j) & 1u) tick[j] = atomicAdd(&hist[r * G + grp[j]], 1u);
+      const uint32_t inc = (use >> j) & 1u;
+      tick[j] = atomicAdd(inc ? &hist[r * G + grp[j]] : ticket_sink, inc);
     }
     if (any_esc) {  // weights too large for a record go straight to the table
 #pragma unroll
-      for (int j = 0; j < kKpt; ++j)
+      for (int j = 0; j < kUse; ++j)
         if ((esc >> j) & 1u) {
           const int64_t sw = a[j] ? -wv[j] : wv[j];
           atomicAdd(&args.table[((size_t)r << args.log2m) + bk[j]], (unsigned long long)sw);
@@ -545,9 +551,9 @@ __device__ __forceinline__ void bin_rows_wave(const BA& args, uint32_t tile, uin
     if (lane < G) d[lane] = off;
     if (lane == G) d[G] = nrec;
 #pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
+    for (int j = 0; j < kUse; ++j) {
       const uint32_t o = __shfl(off, grp[j] & 15u, 64);
-      if (tick[j] != 0xffffffffu) stage[o + tick[j]] = rec[j];
+      *(((use >> j) & 1u) ? &stage[o + tick[j]] : stage_sink) = rec[j];
     }
     wave_lds_sync();
     uint4* out = (uint4*)(args.recs + ((size_t)tile * args.rows + r) * kWaveTile);
@@ -555,6 +561,27 @@ __device__ __forceinline__ void bin_rows_wave(const BA& args, uint32_t tile, uin
     for (uint32_t q = lane; q * 4 < nrec; q += 64) out[q] = st4[q];
     wave_lds_sync();
   }
+}
+
+// The rows of a tile with only the slots that hold keys: `live` (wave-uniform)
+// keys sit in slots 0 .. ceil(live/64) - 1, so the straight-line code is
+// instantiated for 2, 4, 6 and 8 slots and picked once per tile.
+template <int PRIME, int MODE, int K, int NP, bool WIDE, int kKpt, typename BA>
+__device__ __forceinline__ void bin_rows_wave_live(uint32_t live, const BA& args, uint32_t tile, uint32_t G,
+                                                   uint32_t lane, uint32_t* hist, uint32_t* stage,
+                                                   const uint32_t (&x0)[kKpt], const uint32_t (&x1)[kKpt],
+                                                   const int64_t (&wv)[kKpt], const uint32_t (&wpos)[kKpt],
+                                                   const uint32_t (&wneg)[kKpt], uint32_t use, uint32_t esc,
+                                                   bool any_esc) {
+  static_assert(kKpt == 8, "slot variants assume 8 slots per lane");
+  if (live > 6 * 64)
+    bin_rows_wave<PRIME, MODE, K, NP, WIDE, kKpt, 8>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
+  else if (live > 4 * 64)
+    bin_rows_wave<PRIME, MODE, K, NP, WIDE, kKpt, 6>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
+  else if (live > 2 * 64)
+    bin_rows_wave<PRIME, MODE, K, NP, WIDE, kKpt, 4>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
+  else
+    bin_rows_wave<PRIME, MODE, K, NP, WIDE, kKpt, 2>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
 }
 
 // One wave tile of pass 1 (kWaveTile keys of `args`, wave-local LDS `mine`).
@@ -581,6 +608,8 @@ __device__ __forceinline__ uint32_t bin_wave_tile(const BinArgs<KeyT, WT>& args,
     if (DEDUP)
       for (uint32_t i = lane; i < 2 * T; i += 64) slots[i] = 0;
     const uint64_t base = (uint64_t)tile * T;
+    // keys that reach the rows (after combining: the distinct ones), wave-uniform
+    uint32_t live = (uint32_t)min((uint64_t)T, args.n - base);
     uint32_t x0[kKpt], x1[kKpt];
     int64_t wv[kKpt];
     bool ok[kKpt];
@@ -646,6 +675,7 @@ __device__ __forceinline__ uint32_t bin_wave_tile(const BinArgs<KeyT, WT>& args,
         if (lane >= (uint32_t)d) v += t;
       }
       const uint32_t total = __shfl(v, 63, 64);
+      live = __builtin_amdgcn_readfirstlane(total);
       uint32_t pos = v - cnt;
       wave_lds_sync();
 #pragma unroll
@@ -682,9 +712,11 @@ __device__ __forceinline__ uint32_t bin_wave_tile(const BinArgs<KeyT, WT>& args,
     }
     const bool any_esc = __any(esc != 0);
     if (wide)
-      bin_rows_wave<PRIME, MODE, K, NP, true, kKpt>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
+      bin_rows_wave_live<PRIME, MODE, K, NP, true, kKpt>(live, args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg,
+                                                         use, esc, any_esc);
     else
-      bin_rows_wave<PRIME, MODE, K, NP, false, kKpt>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
+      bin_rows_wave_live<PRIME, MODE, K, NP, false, kKpt>(live, args, tile, G, lane, hist, stage, x0, x1, wv, wpos,
+                                                          wneg, use, esc, any_esc);
     }
   return bad;
 }
