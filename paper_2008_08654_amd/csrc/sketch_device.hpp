@@ -288,8 +288,8 @@ __global__ __launch_bounds__(kBlock) void k_update_global(UpdateArgs<KeyT, WT> a
 // tile's region for that row, grouped by range.  A record is
 // (bucket mod R) << wbits | (signed weight mod 2^wbits), wbits = 32 - log2r;
 // a signed weight outside [-2^(wbits-1), 2^(wbits-1)) is added to the global
-// table directly with an atomic instead.  desc[tile][row][0..G] holds the
-// offsets of the groups in the region.
+// table directly with an atomic instead.  The descriptors hold the offsets of
+// the groups in the region, range-major (desc_index).
 // Pass 2 (k_accumulate): persistent blocks take (partition, slice of tiles)
 // items, add the item's records into an int64 LDS table of R counters, then
 // add the non-zero counters into the global table with coalesced atomics.
@@ -465,8 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs<KeyT, WT> args) {
       __syncthreads();
       if (wave == 0) {
         wave_exclusive_scan(hist + r * G, offs, G, lane);
-        uint32_t* d = args.desc + ((size_t)tile * args.rows + r) * (G + 1);
-        for (uint32_t g = lane; g <= G; g += 64) d[g] = offs[g];
+        for (uint32_t g = lane; g <= G; g += 64) args.desc[desc_index(r, g, G, args.tiles, tile)] = offs[g];
       }
       __syncthreads();
 #pragma unroll
@@ -547,9 +546,7 @@ __device__ __forceinline__ void bin_rows_wave(const BA& args, uint32_t tile, uin
     v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);
     const uint32_t off = v - cg;
     const uint32_t nrec = __builtin_amdgcn_readlane(v, G - 1);
-    uint32_t* d = args.desc + ((size_t)tile * args.rows + r) * (G + 1);
-    if (lane < G) d[lane] = off;
-    if (lane == G) d[G] = nrec;
+    if (lane <= G) args.desc[desc_index(r, lane, G, args.tiles, tile)] = lane < G ? off : nrec;
 #pragma unroll
     for (int j = 0; j < kUse; ++j) {
       const uint32_t o = __shfl(off, grp[j] & 15u, 64);

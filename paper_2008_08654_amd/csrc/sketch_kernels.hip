@@ -30,9 +30,8 @@ __device__ __forceinline__ void accumulate_item(const AccArgs& args, uint32_t pa
     for (uint32_t tb = t0 + wave * kU; tb < t1; tb += nw * kU) {
       uint32_t lb = 0, le = 0;
       if (lane < kU && tb + lane < t1) {
-        const uint32_t* d = args.desc + ((size_t)(tb + lane) * args.rows + r) * (G + 1) + g;
-        lb = d[0];
-        le = d[1];
+        lb = args.desc[desc_index(r, g, G, args.tiles, tb + lane)];
+        le = args.desc[desc_index(r, g + 1, G, args.tiles, tb + lane)];
       }
       const uint32_t ntiles = min((uint32_t)kU, t1 - tb);
       uint32_t cur[kU], end[kU];

@@ -151,6 +151,13 @@ struct EstPartial {
   uint32_t big, pad;
 };
 
+// Group bounds of the two-pass workspace, range-major: bound g (0..G) of row
+// `row` of tile `tile` sits at desc[(row * (G + 1) + g) * tiles + tile], so a
+// pass-2 item (row, range) reads the bounds of consecutive tiles contiguously.
+__host__ __device__ inline size_t desc_index(uint32_t row, uint32_t g, uint32_t G, uint32_t tiles, uint32_t tile) {
+  return ((size_t)row * (G + 1) + g) * tiles + tile;
+}
+
 hipError_t launch_update(const UpdatePlan& plan, const UpdateArgsAny& a, hipStream_t st);
 
 // one F2 estimate of a batch: partial-kernel blocks [first_block, first_block +
