@@ -6,14 +6,16 @@
 namespace mcs {
 
 // A record every lane of the wave reads (a work-list entry), kept in scalar
-// registers.
+// registers.  The record must not change during the launch: it is read
+// through the constant address space, which gives scalar loads.
 template <typename T>
 __device__ __forceinline__ T uniform_load(const T* p) {
-  // all lanes read the same record; copy it through readfirstlane
-  T v = *p;
+  static_assert(sizeof(T) % 4 == 0, "records are whole 32-bit words");
+  T v;
   uint32_t* w = reinterpret_cast<uint32_t*>(&v);
+  const auto* q = (const __attribute__((address_space(4))) uint32_t*)p;
 #pragma unroll
-  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(q[i]);
   return v;
 }
 

@@ -38,13 +38,15 @@ struct RowCoeffs {
 template <int K, int NP>
 __device__ __forceinline__ RowCoeffs<K, NP> load_row_coeffs(const uint4* __restrict__ c) {
   RowCoeffs<K, NP> rc;
+  // the coefficients do not change during a launch: read them through the
+  // constant address space, so they come in scalar loads
+  const auto* cc = (const __attribute__((address_space(4))) uint32_t*)c;
 #pragma unroll
   for (int i = 0; i < NP * K; ++i) {
-    const uint4 v = c[i];
-    rc.w[i][0] = __builtin_amdgcn_readfirstlane(v.x);
-    rc.w[i][1] = __builtin_amdgcn_readfirstlane(v.y);
-    rc.w[i][2] = __builtin_amdgcn_readfirstlane(v.z);
-    if (i == 0) rc.r = __builtin_amdgcn_readfirstlane(v.w);
+    rc.w[i][0] = __builtin_amdgcn_readfirstlane(cc[4 * i]);
+    rc.w[i][1] = __builtin_amdgcn_readfirstlane(cc[4 * i + 1]);
+    rc.w[i][2] = __builtin_amdgcn_readfirstlane(cc[4 * i + 2]);
+    if (i == 0) rc.r = __builtin_amdgcn_readfirstlane(cc[3]);
   }
   return rc;
 }
@@ -147,6 +149,40 @@ __device__ __forceinline__ int64_t load_weight(const WT* __restrict__ w, uint64_
   return (int64_t)w[i];
 }
 
+// Keys and weights at positions base + j * stride + tid, j < kKpt.  A position
+// at or past `end` (end > base) loads position end - 1 instead and comes back
+// with ok = false (its key and weight are that position's, so every use must
+// test ok): the loads have no branches and no value is used before all of
+// them are issued.
+template <int kKpt, typename KeyT, typename WT>
+__device__ __forceinline__ void load_tile(const KeyT* __restrict__ keys, const WT* __restrict__ weights, uint64_t base,
+                                          uint32_t stride, uint32_t tid, uint64_t end, uint32_t (&x0)[kKpt],
+                                          uint32_t (&x1)[kKpt], int64_t (&wv)[kKpt], bool (&ok)[kKpt]) {
+  KeyT kr[kKpt];
+  WT wr[kKpt];
+#pragma unroll
+  for (int j = 0; j < kKpt; ++j) {
+    const uint64_t i = base + (uint64_t)j * stride + tid;
+    ok[j] = i < end;
+    const uint64_t at = ok[j] ? i : end - 1;
+    kr[j] = keys[at];
+    wr[j] = weights[at];
+  }
+  // Keep the scheduler from moving uses of the first loads between the others;
+  // the empty statements stop the weights' widening from being fused into
+  // their loads (it would then sit next to each load and wait for it).
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int j = 0; j < kKpt; ++j) asm volatile("" : "+v"(wr[j]));
+#pragma unroll
+  for (int j = 0; j < kKpt; ++j) {
+    const uint64_t k = (uint64_t)kr[j];
+    x0[j] = (uint32_t)k;
+    x1[j] = (uint32_t)(k >> 32);
+    wv[j] = (int64_t)wr[j];
+  }
+}
+
 __device__ __forceinline__ unsigned long long signed_weight(int64_t w, uint32_t a) {
   return (unsigned long long)(a ? -w : w);
 }
@@ -173,17 +209,7 @@ __device__ __forceinline__ void lds_block_update(const UpdateArgs<KeyT, WT>& arg
     uint32_t x0[kKpt], x1[kKpt];
     int64_t wv[kKpt];
     bool ok[kKpt];
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
-      ok[j] = i < end;
-      x0[j] = x1[j] = 0;
-      wv[j] = 0;
-      if (ok[j]) {
-        load_key(args.keys, i, x0[j], x1[j]);
-        wv[j] = load_weight(args.weights, i);
-      }
-    }
+    load_tile<kKpt>(args.keys, args.weights, base, kBlock, threadIdx.x, end, x0, x1, wv, ok);
     uint32_t any_hi = 0;
 #pragma unroll
     for (int j = 0; j < kKpt; ++j) any_hi |= x1[j];
@@ -238,17 +264,7 @@ __device__ __forceinline__ void global_block_update(const UpdateArgs<KeyT, WT>& 
     uint32_t x0[kKpt], x1[kKpt];
     int64_t wv[kKpt];
     bool ok[kKpt];
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
-      ok[j] = i < end;
-      x0[j] = x1[j] = 0;
-      wv[j] = 0;
-      if (ok[j]) {
-        load_key(args.keys, i, x0[j], x1[j]);
-        wv[j] = load_weight(args.weights, i);
-      }
-    }
+    load_tile<kKpt>(args.keys, args.weights, base, kBlock, threadIdx.x, end, x0, x1, wv, ok);
     uint32_t any_hi = 0;
 #pragma unroll
     for (int j = 0; j < kKpt; ++j) any_hi |= x1[j];
@@ -316,6 +332,56 @@ __device__ __forceinline__ uint32_t dedup_slot(uint32_t x0, uint32_t x1) {
   return (x0 * 0x9E3779B1u) ^ (x1 * 0x85EBCA77u) ^ (x0 >> 15);
 }
 
+// Lanes below this one whose bit is set in the wave mask m.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Key combining: inserts a thread's kKpt keys (key j has tile index
+// idx0 + j * stride) into an open-addressing table `slots` (smask + 1 entries
+// of tile index + 1, 0 = empty, linear probing) whose keys and weights are
+// skey/swt by tile index.  The first copy of a key owns its entry; later
+// copies add their weight into the owner's swt.  Each probe round issues the
+// compare-and-swaps of all j together; a settled j re-reads its slot with a
+// compare value no entry holds.  Returns bit j set where key j owns its entry.
+// Ends within smask + 1 rounds when the table holds at most half as many keys.
+template <int kKpt>
+__device__ __forceinline__ uint32_t combine_keys(uint32_t* slots, uint32_t smask, const unsigned long long* skey,
+                                                 long long* swt, const uint32_t (&x0)[kKpt],
+                                                 const uint32_t (&x1)[kKpt], const int64_t (&wv)[kKpt],
+                                                 const bool (&ok)[kKpt], uint32_t idx0, uint32_t stride) {
+  uint32_t h[kKpt], pend = 0, own = 0;
+#pragma unroll
+  for (int j = 0; j < kKpt; ++j) {
+    h[j] = dedup_slot(x0[j], x1[j]) & smask;
+    pend |= (ok[j] ? 1u : 0u) << j;
+  }
+  while (pend) {
+    uint32_t cur[kKpt];
+#pragma unroll
+    for (int j = 0; j < kKpt; ++j)
+      cur[j] = atomicCAS(&slots[h[j]], ((pend >> j) & 1u) ? 0u : 0xffffffffu, idx0 + (uint32_t)j * stride + 1u);
+    unsigned long long other[kKpt];
+#pragma unroll
+    for (int j = 0; j < kKpt; ++j) other[j] = skey[cur[j] ? cur[j] - 1u : 0u];
+#pragma unroll
+    for (int j = 0; j < kKpt; ++j) {
+      if (!((pend >> j) & 1u)) continue;
+      const unsigned long long key = ((unsigned long long)x1[j] << 32) | x0[j];
+      if (cur[j] == 0) {
+        own |= 1u << j;
+        pend &= ~(1u << j);
+      } else if (other[j] == key) {
+        atomicAdd((unsigned long long*)&swt[cur[j] - 1u], (unsigned long long)wv[j]);
+        pend &= ~(1u << j);
+      } else {
+        h[j] = (h[j] + 1u) & smask;
+      }
+    }
+  }
+  return own;
+}
+
 // LDS layout of k_bin: [combining: keys u64[T] | weights i64[T] | slots
 // u32[2T]] | stage u32[T] | hist u32[rows*G] | offs u32[G+1] | spare u32
 // (bin_lds_fixed_bytes() covers the parts before hist).
@@ -347,17 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs<KeyT, WT> args) {
     uint32_t x0[kKpt], x1[kKpt];
     int64_t wv[kKpt];
     bool ok[kKpt];
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
-      ok[j] = i < args.n;
-      x0[j] = x1[j] = 0;
-      wv[j] = 0;
-      if (ok[j]) {
-        load_key(args.keys, i, x0[j], x1[j]);
-        wv[j] = load_weight(args.weights, i);
-      }
-    }
+    load_tile<kKpt>(args.keys, args.weights, base, kBlock, threadIdx.x, args.n, x0, x1, wv, ok);
     uint32_t any_hi = 0;
 #pragma unroll
     for (int j = 0; j < kKpt; ++j) any_hi |= x1[j];
@@ -372,60 +428,37 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs<KeyT, WT> args) {
         swt[idx] = wv[j];
       }
       __syncthreads();
-      uint32_t own = 0;  // bit j: key j is the first copy in the tile
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j) {
-        if (!ok[j]) continue;
-        const uint32_t idx = j * kBlock + threadIdx.x;
-        const unsigned long long key = ((unsigned long long)x1[j] << 32) | x0[j];
-        uint32_t h = dedup_slot(x0[j], x1[j]) & (2 * T - 1);
-        for (uint32_t probe = 0; probe < 2 * T; ++probe) {
-          const uint32_t cur = atomicCAS(&slots[h], 0u, idx + 1);
-          if (cur == 0) {
-            own |= 1u << j;
-            break;
-          }
-          if (skey[cur - 1] == key) {
-            atomicAdd((unsigned long long*)&swt[cur - 1], (unsigned long long)wv[j]);
-            break;
-          }
-          h = (h + 1) & (2 * T - 1);
-        }
-      }
+      // bit j: key j is the first copy in the tile
+      const uint32_t own = combine_keys<kKpt>(slots, 2 * T - 1, skey, swt, x0, x1, wv, ok, threadIdx.x, kBlock);
       __syncthreads();
-      // compact the first copies (with their summed weights) to the front
+      // compact the first copies (with their summed weights) to the front:
+      // wave-local positions from one ballot per j, then the waves' totals
       unsigned long long ck[kKpt];
       long long cw[kKpt];
-      uint32_t mine = 0;
+      uint32_t pos[kKpt], wtotal = 0;
 #pragma unroll
       for (int j = 0; j < kKpt; ++j) {
         const uint32_t idx = j * kBlock + threadIdx.x;
         ck[j] = skey[idx];
         cw[j] = swt[idx];
-        mine += (own >> j) & 1u;
+        const uint64_t m = __ballot((own >> j) & 1u);
+        pos[j] = wtotal + lanes_below(m);
+        wtotal += (uint32_t)__popcll(m);
       }
-      uint32_t v = mine;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += t;
-      }
-      if (lane == 63) stage[wave] = v;  // stage is free until the row loop
+      if (lane == 0) stage[wave] = wtotal;  // stage is free until the row loop
       __syncthreads();
-      uint32_t pos = v - mine;
-      uint32_t total = 0;
+      uint32_t before = 0, total = 0;
       for (uint32_t w = 0; w < kBlock / 64; ++w) {
         const uint32_t c = stage[w];
-        if (w < wave) pos += c;
+        if (w < wave) before += c;
         total += c;
       }
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < kKpt; ++j)
         if ((own >> j) & 1u) {
-          skey[pos] = ck[j];
-          swt[pos] = cw[j];
-          ++pos;
+          skey[before + pos[j]] = ck[j];
+          swt[before + pos[j]] = cw[j];
         }
       __syncthreads();
 #pragma unroll
@@ -610,17 +643,7 @@ __device__ __forceinline__ uint32_t bin_wave_tile(const BinArgs<KeyT, WT>& args,
     uint32_t x0[kKpt], x1[kKpt];
     int64_t wv[kKpt];
     bool ok[kKpt];
-#pragma unroll
-    for (int j = 0; j < kKpt; ++j) {
-      uint64_t i = base + (uint64_t)j * 64 + lane;
-      ok[j] = i < args.n;
-      x0[j] = x1[j] = 0;
-      wv[j] = 0;
-      if (ok[j]) {
-        load_key(args.keys, i, x0[j], x1[j]);
-        wv[j] = load_weight(args.weights, i);
-      }
-    }
+    load_tile<kKpt>(args.keys, args.weights, base, 64, lane, args.n, x0, x1, wv, ok);
     uint32_t any_hi = 0;
 #pragma unroll
     for (int j = 0; j < kKpt; ++j) any_hi |= x1[j];
@@ -634,53 +657,28 @@ __device__ __forceinline__ uint32_t bin_wave_tile(const BinArgs<KeyT, WT>& args,
         swt[idx] = wv[j];
       }
       wave_lds_sync();
-      uint32_t own = 0;
-#pragma unroll
-      for (int j = 0; j < kKpt; ++j) {
-        if (!ok[j]) continue;
-        const uint32_t idx = j * 64 + lane;
-        const unsigned long long key = ((unsigned long long)x1[j] << 32) | x0[j];
-        uint32_t h = dedup_slot(x0[j], x1[j]) & (2 * T - 1);
-        for (uint32_t probe = 0; probe < 2 * T; ++probe) {
-          const uint32_t cur = atomicCAS(&slots[h], 0u, idx + 1);
-          if (cur == 0) {
-            own |= 1u << j;
-            break;
-          }
-          if (skey[cur - 1] == key) {
-            atomicAdd((unsigned long long*)&swt[cur - 1], (unsigned long long)wv[j]);
-            break;
-          }
-          h = (h + 1) & (2 * T - 1);
-        }
-      }
+      const uint32_t own = combine_keys<kKpt>(slots, 2 * T - 1, skey, swt, x0, x1, wv, ok, lane, 64);
       wave_lds_sync();
+      // compact the first copies to the front, positions from one ballot per j
       unsigned long long ck[kKpt];
       long long cw[kKpt];
-      uint32_t cnt = 0;
+      uint32_t pos[kKpt], total = 0;
 #pragma unroll
       for (int j = 0; j < kKpt; ++j) {
         const uint32_t idx = j * 64 + lane;
         ck[j] = skey[idx];
         cw[j] = swt[idx];
-        cnt += (own >> j) & 1u;
+        const uint64_t m = __ballot((own >> j) & 1u);
+        pos[j] = total + lanes_below(m);
+        total += (uint32_t)__popcll(m);
       }
-      uint32_t v = cnt;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += t;
-      }
-      const uint32_t total = __shfl(v, 63, 64);
       live = __builtin_amdgcn_readfirstlane(total);
-      uint32_t pos = v - cnt;
       wave_lds_sync();
 #pragma unroll
       for (int j = 0; j < kKpt; ++j)
         if ((own >> j) & 1u) {
-          skey[pos] = ck[j];
-          swt[pos] = cw[j];
-          ++pos;
+          skey[pos[j]] = ck[j];
+          swt[pos[j]] = cw[j];
         }
       wave_lds_sync();
 #pragma unroll
