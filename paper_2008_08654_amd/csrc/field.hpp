@@ -75,6 +75,12 @@ __device__ __forceinline__ uint64_t p61_final(F61 y) {
   return (v + z) & kP61;
 }
 
+// The low 32 bits of p61_final(y): (v + z) & p agrees with v + z below bit 61.
+__device__ __forceinline__ uint32_t p61_final_lo(F61 y) {
+  const uint64_t v = ((uint64_t)y.w1 << 32) | y.w0;
+  return y.w0 + (uint32_t)((v + 1) >> 61);
+}
+
 // Algorithm 4 for b = 61 and v < 2^122: z = floor(v/p), y = v mod p.
 __device__ __forceinline__ void p61_divmod(uint64_t v_lo, uint64_t v_hi, uint64_t& q, uint64_t& r) {
   unsigned __int128 v = ((unsigned __int128)v_hi << 64) | v_lo;

@@ -51,20 +51,32 @@ __device__ __forceinline__ RowCoeffs<K, NP> load_row_coeffs(const uint4* __restr
   return rc;
 }
 
+// Horner's rule (Algorithm 1) for polynomial q of the row, before the final
+// reduction: a value < 2p congruent to h(x).
 template <int K, int NP>
-__device__ __forceinline__ uint64_t hash61_x32(const RowCoeffs<K, NP>& c, int q, uint32_t x) {
+__device__ __forceinline__ F61 horner61_x32(const RowCoeffs<K, NP>& c, int q, uint32_t x) {
   F61 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
 #pragma unroll
   for (int i = K - 2; i >= 0; --i) y = p61_step_x32(y, x, F61{c.w[q * K + i][0], c.w[q * K + i][1]});
-  return p61_final(y);
+  return y;
+}
+
+template <int K, int NP>
+__device__ __forceinline__ F61 horner61_x64(const RowCoeffs<K, NP>& c, int q, uint32_t x0, uint32_t x1) {
+  F61 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
+#pragma unroll
+  for (int i = K - 2; i >= 0; --i) y = p61_step_x64(y, x0, x1, F61{c.w[q * K + i][0], c.w[q * K + i][1]});
+  return y;
+}
+
+template <int K, int NP>
+__device__ __forceinline__ uint64_t hash61_x32(const RowCoeffs<K, NP>& c, int q, uint32_t x) {
+  return p61_final(horner61_x32<K, NP>(c, q, x));
 }
 
 template <int K, int NP>
 __device__ __forceinline__ uint64_t hash61_x64(const RowCoeffs<K, NP>& c, int q, uint32_t x0, uint32_t x1) {
-  F61 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
-#pragma unroll
-  for (int i = K - 2; i >= 0; --i) y = p61_step_x64(y, x0, x1, F61{c.w[q * K + i][0], c.w[q * K + i][1]});
-  return p61_final(y);
+  return p61_final(horner61_x64<K, NP>(c, q, x0, x1));
 }
 
 template <int K, int NP>
@@ -129,6 +141,22 @@ __device__ __forceinline__ void bucket_sign(const RowCoeffs<K, NP>& c, uint32_t 
       a = h2.w0 & 1u;
       bucket = h.w0 & mask;
     }
+  }
+}
+
+// Bucket and sign bit packed as code = bucket << 1 | a (bits above bit log2m
+// unspecified).  With the low-bit split of Algorithm 3 the reduced hash value
+// already has this layout, so its low word is the code.
+template <int PRIME, int MODE, int K, bool WIDE, int NP>
+__device__ __forceinline__ uint32_t bucket_code(const RowCoeffs<K, NP>& c, uint32_t x0, uint32_t x1, uint32_t log2m) {
+  if constexpr (PRIME == kPrime61 && MODE == kTwoForOne) {
+    return p61_final_lo(WIDE ? horner61_x64<K, NP>(c, 0, x0, x1) : horner61_x32<K, NP>(c, 0, x0));
+  } else if constexpr (PRIME == kPrime89 && MODE == kTwoForOne) {
+    return hash89<K, NP>(c, 0, x0, x1).w0;
+  } else {
+    uint32_t bk, a;
+    bucket_sign<PRIME, MODE, K, WIDE, NP>(c, x0, x1, log2m, bk, a);
+    return (bk << 1) | a;
   }
 }
 
@@ -302,9 +330,11 @@ __global__ __launch_bounds__(kBlock) void k_update_global(UpdateArgs<KeyT, WT> a
 // Pass 1 (k_bin): each block takes tiles of kBinTile keys.  For every row it
 // hashes the tile's keys and writes one 4-byte record per key into the
 // tile's region for that row, grouped by range.  A record is
-// (bucket mod R) << wbits | (signed weight mod 2^wbits), wbits = 32 - log2r;
-// a signed weight outside [-2^(wbits-1), 2^(wbits-1)) is added to the global
-// table directly with an atomic instead.  The descriptors hold the offsets of
+// (bucket mod R) << (wb + 1) | a << wb | (s w mod 2^wb), wb = 31 - log2r,
+// with the sign s = 1 - 2a applied to the weight (pass 2 reads the low wb
+// bits as a signed number; bit wb, the sign bit a, is only carried along).
+// A weight w with |w| >= 2^(wb-1) is added to the global table directly with
+// an atomic instead.  The descriptors hold the offsets of
 // the groups in the region, range-major (desc_index).
 // Pass 2 (k_accumulate): persistent blocks take (partition, slice of tiles)
 // items, add the item's records into an int64 LDS table of R counters, then
@@ -331,6 +361,9 @@ __device__ __forceinline__ void wave_exclusive_scan(const uint32_t* in, uint32_t
 __device__ __forceinline__ uint32_t dedup_slot(uint32_t x0, uint32_t x1) {
   return (x0 * 0x9E3779B1u) ^ (x1 * 0x85EBCA77u) ^ (x0 >> 15);
 }
+
+// Bits of a where m is set, of b elsewhere (one v_bfi_b32).
+__device__ __forceinline__ uint32_t bitsel(uint32_t m, uint32_t a, uint32_t b) { return (m & a) | (~m & b); }
 
 // Lanes below this one whose bit is set in the wave mask m.
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
@@ -397,12 +430,11 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs<KeyT, WT> args) {
   const uint32_t G = 1u << args.log2g;
   uint32_t* offs = hist + args.rows * G;
   uint32_t* count = offs + G + 1;
-  const uint32_t log2r = args.log2r, wbits = 32u - log2r;
+  const uint32_t log2r = args.log2r, wb = 31u - log2r;
   constexpr int kKpt = kBinKpt;
   constexpr int NP = MODE == kTwoPoly ? 2 : 1;
-  const uint32_t rmask = (1u << log2r) - 1u;
-  const uint32_t wmask = (1u << wbits) - 1u;
-  const int64_t half = 1ll << (wbits - 1);
+  const uint32_t wbmask = (1u << wb) - 1u;
+  const int64_t half = 1ll << (wb - 1);
   const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t bad = 0;
   for (uint32_t tile = blockIdx.x; tile < args.tiles; tile += gridDim.x) {
@@ -478,21 +510,20 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs<KeyT, WT> args) {
       uint32_t rec[kKpt], grp[kKpt], tick[kKpt];
 #pragma unroll
       for (int j = 0; j < kKpt; ++j) {
-        uint32_t bk, a;
-        if (wide)
-          bucket_sign<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m, bk, a);
-        else
-          bucket_sign<PRIME, MODE, K, false, NP>(c, x0[j], x1[j], args.log2m, bk, a);
-        int64_t sw = a ? -wv[j] : wv[j];
-        grp[j] = bk >> log2r;
-        rec[j] = ((bk & rmask) << wbits) | ((uint32_t)sw & wmask);
-        const bool fits = (uint64_t)(sw + half) < (2ull * (uint64_t)half);
+        const uint32_t code = wide ? bucket_code<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m)
+                                   : bucket_code<PRIME, MODE, K, false, NP>(c, x0[j], x1[j], args.log2m);
+        grp[j] = __builtin_amdgcn_ubfe(code, 1u + log2r, args.log2g);
+        const int64_t sw = (code & 1u) ? -wv[j] : wv[j];
+        rec[j] = (code << wb) | ((uint32_t)sw & wbmask);
+        const bool fits = wv[j] > -half && wv[j] < half;
         tick[j] = 0xffffffffu;
-        if (ok[j] && sw != 0) {
-          if (fits)
+        if (ok[j] && wv[j] != 0) {
+          if (fits) {
             tick[j] = atomicAdd(&hist[r * G + grp[j]], 1u);
-          else
+          } else {
+            const uint32_t bk = (code >> 1) & ((1u << args.log2m) - 1u);
             atomicAdd(&args.table[((size_t)r << args.log2m) + bk], (unsigned long long)sw);
+          }
         }
       }
       __syncthreads();
@@ -531,59 +562,74 @@ __device__ __forceinline__ void wave_lds_sync() {
 // k_bin with tiles of kWaveTile keys.
 
 // Rows of one wave tile: hash every slot straight-line (no branches, so the
-// slots' Horner chains interleave), take tickets for record-sized weights,
-// prefix the group counts, stage the records in sorted order and copy them
-// out with 16-byte stores.
+// slots' Horner chains interleave), take tickets, prefix the group counts,
+// stage the records in sorted order and copy them out with 16-byte stores.
+// Tickets: a record of range g takes its ticket from counter 2g + c, c the
+// top bit of its bucket mod R (two counters per range halve the lanes that
+// hit one LDS address; the range's records stay contiguous).  A slot without
+// a record (no key, weight 0, or a weight added directly) takes its ticket
+// from spare counter 2G + (lane mod 2G) instead: the spare counters come after
+// the real ones in the staging order and are never copied out, so no slot
+// needs a branch or a select of its addresses.  rmask[j] is ~0 for a slot
+// with a record, else 0; spare is the lane's spare counter.
 template <int PRIME, int MODE, int K, int NP, bool WIDE, int kKpt, int kUse, typename BA>
 __device__ __forceinline__ void bin_rows_wave(const BA& args, uint32_t tile, uint32_t G, uint32_t lane, uint32_t* hist,
                                               uint32_t* stage, const uint32_t (&x0)[kKpt], const uint32_t (&x1)[kKpt],
                                               const int64_t (&wv)[kKpt], const uint32_t (&wpos)[kKpt],
-                                              const uint32_t (&wneg)[kKpt], uint32_t use, uint32_t esc, bool any_esc) {
+                                              const uint32_t (&wdiff)[kKpt], const uint32_t (&rmask)[kKpt],
+                                              uint32_t spare, uint32_t esc, bool any_esc) {
   static_assert(kUse <= kKpt, "more slots than the tile holds");
-  const uint32_t log2r = args.log2r, wbits = 32u - log2r;
-  const uint32_t rmask = (1u << log2r) - 1u;
-  // Lanes without a record in a slot take their ticket from a counter of their
-  // own and stage into a word of their own (words kWaveTile.. of the staging
-  // area, past every record), so the slots need no branches.
-  uint32_t* const stage_sink = stage + kWaveTile + lane;
-  uint32_t* const ticket_sink = stage + kWaveTile + 64 + lane;
+  const uint32_t log2r = args.log2r, wb = 31u - log2r;
+  const uint32_t NC = 4 * G;  // counters per row: 2G real, 2G spare; NC <= 64
   for (uint32_t r = 0; r < args.rows; ++r) {
     const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
-    uint32_t bk[kUse], a[kUse];
+    uint32_t* const hrow = hist + r * NC;
+    uint32_t code[kUse], gq[kUse], tick[kUse];
 #pragma unroll
-    for (int j = 0; j < kUse; ++j) bucket_sign<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m, bk[j], a[j]);
-    uint32_t rec[kUse], grp[kUse], tick[kUse];
+    for (int j = 0; j < kUse; ++j) code[j] = bucket_code<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m);
 #pragma unroll
     for (int j = 0; j < kUse; ++j) {
-      grp[j] = bk[j] >> log2r;
-      rec[j] = ((bk[j] & rmask) << wbits) | (a[j] ? wneg[j] : wpos[j]);
-      const uint32_t inc = (use >> j) & 1u;
-      tick[j] = atomicAdd(inc ? &hist[r * G + grp[j]] : ticket_sink, inc);
+      gq[j] = bitsel(rmask[j], __builtin_amdgcn_ubfe(code[j], log2r, args.log2g + 1u), spare);
+      tick[j] = atomicAdd(&hrow[gq[j]], 4u);  // counts in bytes of staging
     }
     if (any_esc) {  // weights too large for a record go straight to the table
 #pragma unroll
       for (int j = 0; j < kUse; ++j)
         if ((esc >> j) & 1u) {
-          const int64_t sw = a[j] ? -wv[j] : wv[j];
-          atomicAdd(&args.table[((size_t)r << args.log2m) + bk[j]], (unsigned long long)sw);
+          const uint32_t bk = (code[j] >> 1) & ((1u << args.log2m) - 1u);
+          const int64_t sw = (code[j] & 1u) ? -wv[j] : wv[j];
+          atomicAdd(&args.table[((size_t)r << args.log2m) + bk], (unsigned long long)sw);
         }
     }
     wave_lds_sync();
-    // exclusive prefix over the G <= 16 group counts inside the first 16-lane
-    // DPP row (row_shr 1, 2, 4, 8): lane g holds off[g]
-    const uint32_t cg = lane < G ? hist[r * G + lane] : 0u;
+    // exclusive prefix over the NC counters: DPP within 16-lane rows (row_shr
+    // 1, 2, 4, 8), then each later row adds the totals of the rows before it
+    const uint32_t cg = lane < NC ? hrow[lane] : 0u;
     uint32_t v = cg;
     v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false);
     v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);
     v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);
     v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);
+    if (NC > 16) {
+      const uint32_t t0 = __builtin_amdgcn_readlane(v, 15);
+      const uint32_t t1 = t0 + __builtin_amdgcn_readlane(v, 31);
+      const uint32_t t2 = t1 + __builtin_amdgcn_readlane(v, 47);
+      v += lane < 16 ? 0u : lane < 32 ? t0 : lane < 48 ? t1 : t2;
+    }
+    // lane c: byte offset of counter c's records in the staging area; range g
+    // starts at counter 2g, and counter 2G (the first spare) ends the records
     const uint32_t off = v - cg;
-    const uint32_t nrec = __builtin_amdgcn_readlane(v, G - 1);
-    if (lane <= G) args.desc[desc_index(r, lane, G, args.tiles, tile)] = lane < G ? off : nrec;
+    const uint32_t nrec = __builtin_amdgcn_readlane(off, 2 * G) >> 2;
+    const uint32_t goff = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(lane << 3), (int)off);
+    if (lane <= G) args.desc[desc_index(r, lane, G, args.tiles, tile)] = goff >> 2;
+    unsigned char* const stage_b = (unsigned char*)stage;
 #pragma unroll
     for (int j = 0; j < kUse; ++j) {
-      const uint32_t o = __shfl(off, grp[j] & 15u, 64);
-      *(((use >> j) & 1u) ? &stage[o + tick[j]] : stage_sink) = rec[j];
+      const uint32_t o = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(gq[j] << 2), (int)off);
+      // weight field with the sign applied: wneg = wpos ^ wdiff where bit 0 of
+      // the code is set
+      const uint32_t sgn = (uint32_t)__builtin_amdgcn_sbfe((int)code[j], 0, 1);
+      *(uint32_t*)(stage_b + o + tick[j]) = (code[j] << wb) | (wpos[j] ^ (wdiff[j] & sgn));
     }
     wave_lds_sync();
     uint4* out = (uint4*)(args.recs + ((size_t)tile * args.rows + r) * kWaveTile);
@@ -601,17 +647,17 @@ __device__ __forceinline__ void bin_rows_wave_live(uint32_t live, const BA& args
                                                    uint32_t lane, uint32_t* hist, uint32_t* stage,
                                                    const uint32_t (&x0)[kKpt], const uint32_t (&x1)[kKpt],
                                                    const int64_t (&wv)[kKpt], const uint32_t (&wpos)[kKpt],
-                                                   const uint32_t (&wneg)[kKpt], uint32_t use, uint32_t esc,
-                                                   bool any_esc) {
+                                                   const uint32_t (&wdiff)[kKpt], const uint32_t (&rmask)[kKpt],
+                                                   uint32_t spare, uint32_t esc, bool any_esc) {
   static_assert(kKpt == 8, "slot variants assume 8 slots per lane");
   if (live > 6 * 64)
-    bin_rows_wave<PRIME, MODE, K, NP, WIDE, kKpt, 8>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
+    bin_rows_wave<PRIME, MODE, K, NP, WIDE, kKpt, 8>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wdiff, rmask, spare, esc, any_esc);
   else if (live > 4 * 64)
-    bin_rows_wave<PRIME, MODE, K, NP, WIDE, kKpt, 6>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
+    bin_rows_wave<PRIME, MODE, K, NP, WIDE, kKpt, 6>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wdiff, rmask, spare, esc, any_esc);
   else if (live > 2 * 64)
-    bin_rows_wave<PRIME, MODE, K, NP, WIDE, kKpt, 4>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
+    bin_rows_wave<PRIME, MODE, K, NP, WIDE, kKpt, 4>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wdiff, rmask, spare, esc, any_esc);
   else
-    bin_rows_wave<PRIME, MODE, K, NP, WIDE, kKpt, 2>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg, use, esc, any_esc);
+    bin_rows_wave<PRIME, MODE, K, NP, WIDE, kKpt, 2>(args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wdiff, rmask, spare, esc, any_esc);
 }
 
 // One wave tile of pass 1 (kWaveTile keys of `args`, wave-local LDS `mine`).
@@ -628,13 +674,12 @@ __device__ __forceinline__ uint32_t bin_wave_tile(const BinArgs<KeyT, WT>& args,
   uint32_t* slots = (uint32_t*)(mine + (DEDUP ? T * 16 : 0));
   uint32_t* stage = slots;  // reused once the combining table is no longer needed
   uint32_t* hist = slots + 2 * T;
-  const uint32_t log2r = args.log2r, wbits = 32u - log2r;
-  const uint32_t rmask = (1u << log2r) - 1u;
-  const uint32_t wmask = (1u << wbits) - 1u;
-  const int64_t half = 1ll << (wbits - 1);
+  const uint32_t wb = 31u - args.log2r;
+  const uint32_t wbmask = (1u << wb) - 1u;
+  const int64_t half = 1ll << (wb - 1);
   uint32_t bad = 0;
   {
-    for (uint32_t i = lane; i < args.rows * G; i += 64) hist[i] = 0;
+    for (uint32_t i = lane; i < args.rows * 4 * G; i += 64) hist[i] = 0;
     if (DEDUP)
       for (uint32_t i = lane; i < 2 * T; i += 64) slots[i] = 0;
     const uint64_t base = (uint64_t)tile * T;
@@ -693,25 +738,27 @@ __device__ __forceinline__ uint32_t bin_wave_tile(const BinArgs<KeyT, WT>& args,
       wave_lds_sync();
     }
     const bool wide = PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0);
-    // per key, independent of the row: record-sized weights (both signs fit
-    // the record field) and the weight's field for both signs
-    uint32_t use = 0, esc = 0;  // bit j: key j goes into a record / is added directly
-    uint32_t wpos[kKpt], wneg[kKpt];
+    // per key, independent of the row: the record's weight field for both
+    // signs, whether the key has a record, its spare group, and the weights
+    // added directly
+    uint32_t esc = 0;  // bit j: key j's weight is added directly
+    uint32_t wpos[kKpt], wdiff[kKpt], rmask[kKpt];
+    const uint32_t spare = 2 * G + (lane & (2 * G - 1));
 #pragma unroll
     for (int j = 0; j < kKpt; ++j) {
-      const bool small = wv[j] > -half && wv[j] < half;
-      use |= (ok[j] && wv[j] != 0 && small ? 1u : 0u) << j;
-      esc |= (ok[j] && !small ? 1u : 0u) << j;
-      wpos[j] = (uint32_t)wv[j] & wmask;
-      wneg[j] = (uint32_t)(-wv[j]) & wmask;
+      const bool fits = wv[j] > -half && wv[j] < half;
+      rmask[j] = ok[j] && wv[j] != 0 && fits ? ~0u : 0u;
+      esc |= (ok[j] && !fits ? 1u : 0u) << j;
+      wpos[j] = (uint32_t)wv[j] & wbmask;
+      wdiff[j] = wpos[j] ^ ((uint32_t)(-wv[j]) & wbmask);
     }
     const bool any_esc = __any(esc != 0);
     if (wide)
-      bin_rows_wave_live<PRIME, MODE, K, NP, true, kKpt>(live, args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wneg,
-                                                         use, esc, any_esc);
+      bin_rows_wave_live<PRIME, MODE, K, NP, true, kKpt>(live, args, tile, G, lane, hist, stage, x0, x1, wv, wpos, wdiff,
+                                                         rmask, spare, esc, any_esc);
     else
       bin_rows_wave_live<PRIME, MODE, K, NP, false, kKpt>(live, args, tile, G, lane, hist, stage, x0, x1, wv, wpos,
-                                                          wneg, use, esc, any_esc);
+                                                          wdiff, rmask, spare, esc, any_esc);
     }
   return bad;
 }

@@ -14,7 +14,7 @@ namespace mcs {
 __device__ __forceinline__ void accumulate_item(const AccArgs& args, uint32_t part, uint32_t slice,
                                                 unsigned long long* acc) {
   const uint32_t G = 1u << args.log2g;
-  const uint32_t log2r = args.log2r, wbits = 32u - log2r;
+  const uint32_t log2r = args.log2r, wb = 31u - log2r;  // weight field bits (record layout in k_bin)
   const uint32_t span = args.log2m < log2r ? (1u << args.log2m) : (1u << log2r);  // counters per range
   const uint32_t per = (args.tiles + args.slices - 1) / args.slices;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
@@ -55,8 +55,8 @@ __device__ __forceinline__ void accumulate_item(const AccArgs& args, uint32_t pa
 #pragma unroll
         for (int u = 0; u < kU; ++u)
           if (has[u]) {
-            int64_t sw = (int64_t)((int32_t)(v[u] << log2r) >> log2r);
-            atomicAdd(&acc[v[u] >> wbits], (unsigned long long)sw);
+            const int64_t sw = (int64_t)((int32_t)(v[u] << (log2r + 1)) >> (log2r + 1));
+            atomicAdd(&acc[v[u] >> (wb + 1)], (unsigned long long)sw);
           }
         more = false;
 #pragma unroll

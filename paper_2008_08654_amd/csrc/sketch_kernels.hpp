@@ -243,13 +243,14 @@ hipError_t set_batch_acc_attribute();
 
 // LDS bytes of one wave of the wave-tile pass 1:
 //   [combining: keys u64[T] | weights i64[T]] | slots u32[2T] (records are
-//   staged there) | counters u32[rows*G], padded to 16 bytes.
+//   staged there) | ticket counters u32[rows*4G] (two per range, then the
+//   spare ones), padded to 16 bytes.
 // Each wave's region starts at wave * this stride, so the stride must keep the
 // 8-byte key/weight arrays (64-bit LDS atomics need natural alignment) and the
 // 16-byte staged copies aligned for every wave, whatever rows * G is.
 template <bool DEDUP>
 __host__ __device__ constexpr uint32_t binw_lds_per_wave(uint32_t rows, uint32_t G) {
-  return (DEDUP ? kWaveTile * 16 : 0) + 2 * kWaveTile * 4 + ((rows * G * 4 + 15u) & ~15u);
+  return (DEDUP ? kWaveTile * 16 : 0) + 2 * kWaveTile * 4 + ((rows * 4 * G * 4 + 15u) & ~15u);
 }
 
 // LDS bytes of the pass-1 kernel besides the per-row counters
