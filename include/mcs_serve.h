@@ -38,8 +38,9 @@ typedef struct {
   /* Most update keys one step takes (0: 2^26).  A request with more keys
    * runs in a step of its own. */
   uint64_t step_keys;
-  /* Two-pass workspace of a step in bytes (0: 256 MiB); a step whose records
-   * exceed it runs in several rounds over the same workspace. */
+  /* Two-pass workspace of a step in bytes (0: 2 GiB, enough for the records
+   * of a full default step in one round); a step whose records exceed it
+   * runs in several rounds over the same workspace. */
   uint64_t work_bytes;
   /* An update with n < direct_fraction * buckets keys goes to the table with
    * direct atomics instead of the two-pass update (as in cs_batch_options;

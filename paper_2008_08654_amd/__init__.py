@@ -309,6 +309,16 @@ class Batch:
 CS_REQ_UPDATE, CS_REQ_F2 = 0, 1
 
 
+class PreparedRequests:
+    """Requests marshalled once for Server.replay (see Server.prepare)."""
+
+    def __init__(self, array, n, keep):
+        self.array, self.n, self._keep = array, n, keep
+
+    def __len__(self):
+        return self.n
+
+
 class ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("step_keys", ctypes.c_uint64), ("work_bytes", ctypes.c_uint64),
                 ("direct_fraction", ctypes.c_double)]
@@ -398,21 +408,36 @@ class Server:
         _check(lib().cs_server_get_stats(self._h, ctypes.byref(out)))
         return out
 
-    def replay(self, requests, arrival_s) -> list:
-        """requests: list of (tenant, kind, keys, weights) with device tensors (None for F2);
-        arrival_s: non-decreasing seconds after the call starts.  Returns ServerResult per request."""
+    def prepare(self, requests) -> "PreparedRequests":
+        """Marshals requests, a list of (tenant, kind, keys, weights) with device tensors
+        (None for F2), into the C array cs_server_replay takes; replay() then skips this
+        work.  The tensors are referenced until the returned object is dropped."""
         n = len(requests)
         reqs = (ServerRequest * n)()
+        keep = []
         for i, (tenant, kind, keys, weights) in enumerate(requests):
             reqs[i].tenant, reqs[i].kind = tenant, kind
             if kind == CS_REQ_UPDATE and keys is not None and keys.numel():
                 if _key_dtype(keys) != self._kt or _weight_dtype(weights) != self._wt:
                     raise ValueError("key or weight dtype differs from the server's")
                 reqs[i].keys, reqs[i].weights, reqs[i].n = keys.data_ptr(), weights.data_ptr(), keys.numel()
-        arr = (ctypes.c_double * n)(*[float(a) for a in arrival_s])
+                keep.append((keys, weights))
+        return PreparedRequests(reqs, n, keep)
+
+    def replay(self, requests, arrival_s):
+        """requests: a list as for prepare(), or its result; arrival_s: non-decreasing seconds
+        after the call starts (a sequence or a float64 array).  Returns one ServerResult per
+        request (a ctypes array)."""
+        if not isinstance(requests, PreparedRequests):
+            requests = self.prepare(requests)
+        n = requests.n
+        arr = np.ascontiguousarray(np.asarray(arrival_s, dtype=np.float64))
+        if arr.shape != (n,):
+            raise ValueError("one arrival time per request")
         res = (ServerResult * n)()
-        _check(lib().cs_server_replay(self._h, reqs, n, arr, res))
-        return list(res)
+        _check(lib().cs_server_replay(self._h, requests.array, n,
+                                      arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), res))
+        return res
 
     def close(self):
         if self._h:

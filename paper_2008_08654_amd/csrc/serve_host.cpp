@@ -6,8 +6,11 @@
 // key limit) become one batched update (the classes and kernels of the
 // batched path, planned per step, launched without a graph since every step
 // has another shape), and the step's F2 requests are estimated after it.  A
-// tenant's update that arrives after one of its F2 requests closes the step,
-// so every answer sees exactly the updates submitted before it.  Two steps can
+// tenant's update that arrives after one of its F2 requests in the step waits
+// for a later step, and so does every later request of that tenant; other
+// tenants' requests behind it still join the step.  So each tenant's requests
+// in a step are a prefix of its queued requests with its updates before its
+// F2 requests, and every answer sees exactly the updates submitted before it.  Two steps can
 // be in flight: the next is planned and enqueued while the GPU runs the
 // previous one; each has its own work-list buffers, and both share the
 // two-pass workspace, which stream order makes safe.
@@ -37,10 +40,11 @@ namespace {
 
 constexpr uint64_t kDefaultBudget = 64ull << 30;
 constexpr uint64_t kDefaultStepKeys = 1ull << 26;
-constexpr uint64_t kDefaultWork = 256ull << 20;
+constexpr uint64_t kDefaultWork = 2ull << 30;
 constexpr size_t kListsInit = 4u << 20;
 constexpr size_t kResultWords = 32768;  // pinned int64 F2 outputs per step
 constexpr int kDepth = 2;               // steps in flight
+constexpr size_t kScanMax = 16384;      // queued requests one step looks at
 // Served tables are mostly far larger than the last-level cache, where
 // random 64-bit atomics cost much more than pass 2's coalesced flushes: only
 // the shortest updates take them.
@@ -154,37 +158,57 @@ bool alloc_lists(Slot& sl, size_t bytes) {
   return true;
 }
 
-// Takes the next step's requests from the queue (lock held).
+// Takes the next step's requests from the queue (lock held).  A request that
+// cannot join (its tenant's F2 is in the step, the key or result limit is
+// reached, or an earlier request of its tenant was held back) is held back
+// and stays queued, in order, ahead of the requests not looked at.
 void form_step(cs_server* S, Step& st) {
   std::unordered_map<uint32_t, size_t> queried;  // tenant -> its estimate's offset
-  while (!S->queue.empty()) {
-    const Request& r = S->queue.front();
-    if (r.kind == CS_REQ_UPDATE) {
-      if (queried.count(r.tenant)) break;  // this tenant's F2 must not see it
-      if (!st.reqs.empty() && st.keys + r.n > S->step_keys) break;
-      st.keys += r.n;
-      S->queued_keys -= r.n;
-      st.res_off.push_back(SIZE_MAX);
-      st.rows.push_back(0);
-    } else {
+  std::unordered_set<uint32_t> held;             // tenants with a request held back
+  std::vector<Request> back;
+  size_t scanned = 0;
+  while (!S->queue.empty() && scanned < kScanMax) {
+    const Request r = S->queue.front();
+    S->queue.pop_front();
+    ++scanned;
+    bool take = !held.count(r.tenant);
+    if (take && r.kind == CS_REQ_UPDATE) {
+      // this tenant's F2 must not see it; the step's keys are full
+      take = !queried.count(r.tenant) && (st.reqs.empty() || st.keys + r.n <= S->step_keys);
+      if (take) {
+        st.keys += r.n;
+        S->queued_keys -= r.n;
+        st.res_off.push_back(SIZE_MAX);
+        st.rows.push_back(0);
+      }
+    } else if (take) {
       const uint32_t rows = S->tenants[r.tenant]->sk->rows;
       auto it = queried.find(r.tenant);
-      size_t off;
+      size_t off = 0;
       if (it != queried.end()) {
         off = it->second;  // same tenant, no update in between: same answer
+      } else if (st.result_words + rows + 2 > kResultWords) {
+        take = false;
       } else {
-        if (st.result_words + rows + 2 > kResultWords) break;
         off = st.result_words;
         st.result_words += rows + 2;
         queried.emplace(r.tenant, off);
         st.estimates.emplace_back(r.tenant, off);
       }
-      st.res_off.push_back(off);
-      st.rows.push_back(rows);
+      if (take) {
+        st.res_off.push_back(off);
+        st.rows.push_back(rows);
+      }
     }
-    st.reqs.push_back(r);
-    S->queue.pop_front();
+    if (take) {
+      st.reqs.push_back(r);
+    } else {
+      held.insert(r.tenant);
+      back.push_back(r);
+    }
+    if (st.keys >= S->step_keys) break;  // no further update fits
   }
+  S->queue.insert(S->queue.begin(), back.begin(), back.end());
 }
 
 // Plans and enqueues a step on the server's stream (lock not held): one

@@ -149,15 +149,20 @@ def test_served_admission_budget_and_eviction():
     srv.close()
 
 
-def test_served_open_loop_replay():
+@pytest.mark.parametrize("prepared", [False, True])
+def test_served_open_loop_replay(prepared):
     seed0 = 950
     reqs = _trace(240, W.DATA_SEED + 51, max_log2=14.0)
     _, want_f2 = _oracle_answers(reqs, seed0)
     srv = M.Server(step_keys=1 << 15)
     ids = _admit_all(srv, seed0)
-    arrivals = W.poisson_arrivals(len(reqs), 20000.0, seed=W.DATA_SEED + 51).tolist()
+    arrivals = W.poisson_arrivals(len(reqs), 20000.0, seed=W.DATA_SEED + 51)
     mapped = [(ids[t], kind, k, w) for t, kind, k, w in reqs]
-    res = srv.replay(mapped, arrivals)
+    if prepared:  # marshalled once, arrivals as a float64 array
+        res = srv.replay(srv.prepare(mapped), arrivals.numpy())
+    else:
+        res = srv.replay(mapped, arrivals.tolist())
+    assert len(res) == len(reqs)
     assert all(r.status == O.OK or i in want_f2 for i, r in enumerate(res))
     for i, (st, med) in want_f2.items():
         assert res[i].status == st and (st != O.OK or res[i].f2 == med), i
