@@ -314,12 +314,21 @@ UpdatePlan mcs::plan_update(const cs_sketch* s, uint64_t n) {
     p.dedup = s->combine;
     const uint32_t G = 1u << log2g;
     p.wave_tiles = G <= 16 && s->rows <= 16;
-    if (p.wave_tiles)
-      p.lds_bytes = (kBlock / 64) * (p.dedup ? binw_lds_per_wave<true>(s->rows, G)
-                                             : binw_lds_per_wave<false>(s->rows, G));
-    else
-      p.lds_bytes = (p.dedup ? bin_lds_fixed_bytes<true>() : bin_lds_fixed_bytes<false>()) +
-                    (uint32_t)(((uint64_t)s->rows * G + G + 2) * 4);
+    // On the automatic path a probe of the keys chooses combining for block
+    // tiles, whose combining table halves the occupancy; wave tiles combine
+    // at little cost and always do.
+    p.combine_auto = s->path == CS_PATH_AUTO && s->combine && !p.wave_tiles;
+    uint32_t with = 0, without = 0;
+    if (p.wave_tiles) {
+      with = (kBlock / 64) * binw_lds_per_wave<true>(s->rows, G);
+      without = (kBlock / 64) * binw_lds_per_wave<false>(s->rows, G);
+    } else {
+      const uint32_t counters = (uint32_t)(((uint64_t)s->rows * G + G + 2) * 4);
+      with = bin_lds_fixed_bytes<true>() + counters;
+      without = bin_lds_fixed_bytes<false>() + counters;
+    }
+    p.lds_bytes = p.dedup ? with : without;
+    p.lds_bytes_plain = without;
     const uint32_t span = 1u << std::min(log2r, s->log2m);
     p.acc_lds_bytes = span * 8;
     const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(2, kLdsPerCu / p.acc_lds_bytes));
@@ -377,7 +386,8 @@ cs_status mcs::enqueue_update(cs_sketch* s, const UpdatePlan& plan, const void* 
     const uint64_t tiles_c = (chunk + tk - 1) / tk;
     const size_t rec_bytes = (size_t)tiles_c * s->rows * tk * 4;
     const size_t desc_bytes = (size_t)tiles_c * s->rows * (G + 1) * 4;
-    cs_status st = ensure_workspace(s, rec_bytes + desc_bytes);
+    const size_t probe_bytes = plan.combine_auto ? 2 * kProbeTiles * sizeof(uint32_t) : 0;
+    cs_status st = ensure_workspace(s, rec_bytes + desc_bytes + probe_bytes);
     if (st != CS_OK) return st;
     for (uint64_t off = 0; off < n; off += chunk) {
       const uint64_t len = std::min<uint64_t>(chunk, n - off);
@@ -392,6 +402,7 @@ cs_status mcs::enqueue_update(cs_sketch* s, const UpdatePlan& plan, const void* 
       p.acc_slices = (uint32_t)slices;
       p.recs = (uint32_t*)s->d_work;
       p.desc = (uint32_t*)((char*)s->d_work + rec_bytes);
+      p.probe = plan.combine_auto ? (uint32_t*)((char*)s->d_work + rec_bytes + desc_bytes) : nullptr;
       a.keys = (const char*)keys + off * kb;
       a.weights = (const char*)weights + off * wb;
       a.n = len;

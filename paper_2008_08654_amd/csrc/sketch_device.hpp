@@ -415,11 +415,28 @@ __device__ __forceinline__ uint32_t combine_keys(uint32_t* slots, uint32_t smask
   return own;
 }
 
+// Whether key combining pays on a launch's keys: fewer than permille / 1000
+// of the keys in the probe's sample windows are distinct (k_combine_probe).
+// Wave-uniform.
+__device__ __forceinline__ bool combine_pays(const uint32_t* probe, uint32_t samples, uint32_t permille) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t d = lane < samples ? probe[lane] : 0u;
+  uint32_t c = lane < samples ? probe[kProbeTiles + lane] : 0u;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    d += __shfl_xor(d, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  return (uint64_t)__builtin_amdgcn_readfirstlane(d) * 1000 < (uint64_t)__builtin_amdgcn_readfirstlane(c) * permille;
+}
+
 // LDS layout of k_bin: [combining: keys u64[T] | weights i64[T] | slots
 // u32[2T]] | stage u32[T] | hist u32[rows*G] | offs u32[G+1] | spare u32
 // (bin_lds_fixed_bytes() covers the parts before hist).
 template <int PRIME, int MODE, int K, typename KeyT, typename WT, bool DEDUP>
 __global__ __launch_bounds__(kBlock) void k_bin(BinArgs<KeyT, WT> args) {
+  // every wave takes the same choice, so a block leaves before any barrier
+  if (args.probe && combine_pays(args.probe, args.probe_tiles, args.probe_permille) != DEDUP) return;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr uint32_t T = kBinTile;
   unsigned long long* skey = (unsigned long long*)smem;          // DEDUP
@@ -765,6 +782,7 @@ __device__ __forceinline__ uint32_t bin_wave_tile(const BinArgs<KeyT, WT>& args,
 
 template <int PRIME, int MODE, int K, typename KeyT, typename WT, bool DEDUP>
 __global__ __launch_bounds__(kBlock) void k_bin_wave(BinArgs<KeyT, WT> args) {
+  if (args.probe && combine_pays(args.probe, args.probe_tiles, args.probe_permille) != DEDUP) return;
   extern __shared__ __align__(16) unsigned char smem[];
   // wave index made explicitly uniform so the tile loop, the row loop and the
   // coefficient loads stay scalar
@@ -775,6 +793,50 @@ __global__ __launch_bounds__(kBlock) void k_bin_wave(BinArgs<KeyT, WT> args) {
   for (uint32_t tile = blockIdx.x * (kBlock / 64) + wave; tile < args.tiles; tile += nw)
     bad |= bin_wave_tile<PRIME, MODE, K, KeyT, WT, DEDUP>(args, tile, lane, mine);
   if (bad) atomicOr(args.flags, kFlagDomain);
+}
+
+// Combining probe: block b (one wave) combines the 512-key window
+// floor(b * windows / samples) of the keys exactly as pass 1 would and writes
+// its distinct and total key counts to probe[b] and probe[kProbeTiles + b]
+// (samples <= min(kProbeTiles, windows)).
+template <typename KeyT>
+__global__ __launch_bounds__(64) void k_combine_probe(const KeyT* __restrict__ keys, uint64_t n, uint32_t samples,
+                                                      uint32_t* __restrict__ probe) {
+  constexpr uint32_t T = kWaveTile;
+  constexpr int kKpt = T / 64;
+  __shared__ unsigned long long skey[T];
+  __shared__ long long swt[T];
+  __shared__ uint32_t slots[2 * T];
+  const uint32_t lane = threadIdx.x;
+  const uint64_t windows = (n + T - 1) / T;
+  const uint64_t base = (uint64_t)blockIdx.x * windows / samples * T;
+  for (uint32_t i = lane; i < 2 * T; i += 64) slots[i] = 0;
+  uint32_t x0[kKpt], x1[kKpt];
+  int64_t wv[kKpt];
+  bool ok[kKpt];
+#pragma unroll
+  for (int j = 0; j < kKpt; ++j) {
+    const uint64_t i = base + (uint64_t)j * 64 + lane;
+    ok[j] = i < n;
+    const uint64_t k = ok[j] ? (uint64_t)keys[i] : 0ull;
+    x0[j] = (uint32_t)k;
+    x1[j] = (uint32_t)(k >> 32);
+    wv[j] = 0;
+    skey[j * 64 + lane] = k;
+    swt[j * 64 + lane] = 0;
+  }
+  wave_lds_sync();
+  const uint32_t own = combine_keys<kKpt>(slots, 2 * T - 1, skey, swt, x0, x1, wv, ok, lane, 64);
+  uint32_t distinct = 0, total = 0;
+#pragma unroll
+  for (int j = 0; j < kKpt; ++j) {
+    distinct += (uint32_t)__popcll(__ballot((own >> j) & 1u));
+    total += (uint32_t)__popcll(__ballot(ok[j]));
+  }
+  if (lane == 0) {
+    probe[blockIdx.x] = distinct;
+    probe[kProbeTiles + blockIdx.x] = total;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -938,18 +1000,34 @@ hipError_t launch_update_t(const UpdatePlan& plan, const UpdateArgs<KeyT, WT>& a
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       attr_set = true;
     }
-    if (plan.wave_tiles) {
-      if (plan.dedup)
-        hipLaunchKernelGGL((k_bin_wave<PRIME, MODE, K, KeyT, WT, true>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, b);
+    auto launch_bin = [&](bool dedup, uint32_t lds) {
+      if (plan.wave_tiles && dedup)
+        hipLaunchKernelGGL((k_bin_wave<PRIME, MODE, K, KeyT, WT, true>), dim3(plan.blocks), dim3(kBlock), lds, st, b);
+      else if (plan.wave_tiles)
+        hipLaunchKernelGGL((k_bin_wave<PRIME, MODE, K, KeyT, WT, false>), dim3(plan.blocks), dim3(kBlock), lds, st, b);
+      else if (dedup)
+        hipLaunchKernelGGL((k_bin<PRIME, MODE, K, KeyT, WT, true>), dim3(plan.blocks), dim3(kBlock), lds, st, b);
       else
-        hipLaunchKernelGGL((k_bin_wave<PRIME, MODE, K, KeyT, WT, false>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, b);
-    } else if (plan.dedup) {
-      hipLaunchKernelGGL((k_bin<PRIME, MODE, K, KeyT, WT, true>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, b);
-    } else {
-      hipLaunchKernelGGL((k_bin<PRIME, MODE, K, KeyT, WT, false>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, b);
+        hipLaunchKernelGGL((k_bin<PRIME, MODE, K, KeyT, WT, false>), dim3(plan.blocks), dim3(kBlock), lds, st, b);
+      return hipGetLastError();
+    };
+    hipError_t e;
+    if (plan.combine_auto) {
+      // The probe decides on the device; of the two pass-1 launches the one
+      // that does not match leaves at once.  Block tiles need more duplicates
+      // than wave tiles to gain: their combining table costs occupancy.
+      const uint64_t windows = (a.n + kWaveTile - 1) / kWaveTile;
+      const uint32_t samples = (uint32_t)std::min<uint64_t>(kProbeTiles, windows);
+      hipLaunchKernelGGL((k_combine_probe<KeyT>), dim3(samples), dim3(64), 0, st, a.keys, a.n, samples, plan.probe);
+      b.probe = plan.probe;
+      b.probe_tiles = samples;
+      b.probe_permille = plan.wave_tiles ? 900 : 750;
+      if ((e = hipGetLastError()) != hipSuccess || (e = launch_bin(true, plan.lds_bytes)) != hipSuccess ||
+          (e = launch_bin(false, plan.lds_bytes_plain)) != hipSuccess)
+        return e;
+    } else if ((e = launch_bin(plan.dedup, plan.lds_bytes)) != hipSuccess) {
+      return e;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     AccArgs c{plan.recs, plan.desc, plan.tiles, a.rows, a.log2m, plan.log2g, plan.log2r, plan.acc_slices,
               plan.wave_tiles ? kWaveTile : kBinTile, a.table};
     return launch_accumulate(c, plan.acc_blocks, plan.acc_lds_bytes, st);

@@ -33,6 +33,7 @@ constexpr int kVariantBinned = 2;
 // two-pass (binned) update
 constexpr int kBinKpt = 8;                          // keys per thread in a pass-1 tile
 constexpr uint32_t kBinTile = kBlock * kBinKpt;     // keys per tile (block tiles)
+constexpr uint32_t kProbeTiles = 64;               // 512-key windows sampled by the combining probe
 constexpr uint32_t kWaveTile = 512;                 // keys per tile (wave tiles, <= 16 ranges per row)
 constexpr uint32_t kMinRangeLog2 = 11;              // counters per partition: 2^11 .. 2^14 (int64 LDS in pass 2)
 constexpr uint32_t kMaxRangeLog2 = 14;
@@ -51,6 +52,9 @@ struct UpdatePlan {
   uint32_t acc_blocks;  // pass-2 persistent blocks
   uint32_t acc_lds_bytes;
   bool dedup;           // combine repeated keys of a tile before hashing
+  bool combine_auto;    // probe the keys, then launch both pass-1 variants (dedup ignored)
+  uint32_t lds_bytes_plain;  // pass-1 LDS of the variant without combining (combine_auto)
+  uint32_t* probe;           // kProbeTiles * 2 words of device memory (combine_auto)
   bool wave_tiles;      // pass 1 with one tile per wave (k_bin_wave)
   uint32_t* recs;       // [tiles][rows][kBinTile]
   uint32_t* desc;       // [tiles][rows][G + 1]
@@ -103,6 +107,11 @@ struct BinArgs {
   uint32_t* desc;
   unsigned long long* table;
   uint32_t* flags;
+  // When probe is set, the launch runs only if its combining choice is the
+  // probe's (combine_pays); the other variant is launched beside it.
+  const uint32_t* probe;
+  uint32_t probe_tiles;
+  uint32_t probe_permille;
 };
 
 struct AccArgs {

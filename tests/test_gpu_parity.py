@@ -161,6 +161,27 @@ def test_combining_repeated_keys_exact(path):
     _check_sketch(sk, keys, w)
 
 
+@pytest.mark.parametrize("log2m,prime", [(16, 1), (20, 2)])  # wave tiles, block tiles
+@pytest.mark.parametrize("kind", ["uniform", "zipf", "one_key"])
+@pytest.mark.parametrize("n", [100, 5 * 2048 + 77])
+def test_automatic_combining_choice_matches_oracle(log2m, prime, kind, n):
+    """The automatic path probes the keys and runs pass 1 with or without combining
+    (uniform keys: without; repeated keys: with); the counters are the oracle's either way."""
+    if kind == "uniform":
+        keys = W.uniform_u64(70, n)
+        if prime == 1:
+            keys = keys & ((1 << 60) - 1)
+    elif kind == "zipf":
+        keys = W.zipf(71, n, 1.1, 1 << 32)
+    else:
+        keys = torch.full((n,), 123456789, dtype=torch.int64)
+    w = W.bounded_int(72, n, -100, 100)
+    keys, w = keys.to(DEV), w.to(DEV)
+    sk = _make(4, 1 << log2m, prime, 73)
+    sk.update(keys, w)
+    _check_sketch(sk, keys, w)
+
+
 def test_lds_path_forced_on_small_table():
     keys, w = W.stream_zipf_u64(10000, seed=3)
     keys, w = keys.to(DEV), w.to(DEV)
