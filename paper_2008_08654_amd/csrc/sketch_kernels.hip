@@ -9,8 +9,15 @@
 
 namespace mcs {
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 // One pass-2 item: records of partition `part` from the tiles of slice
-// `slice`, accumulated in LDS `acc` and added into args.table.
+// `slice`, accumulated in LDS `acc` and added into args.table.  A wave takes
+// kU tiles at a time.  Each lane loads 16-byte chunks (4 records), 16 lanes
+// per tile, so one load reads up to 64 records of each of 4 tiles; the
+// kU / 4 loads of a round are issued before any record is used (a lane with
+// no chunk of its tile loads a harmless chunk instead of branching), and
+// each record of a chunk is kept only if it lies in the tile's group.
 __device__ __forceinline__ void accumulate_item(const AccArgs& args, uint32_t part, uint32_t slice,
                                                 unsigned long long* acc) {
   const uint32_t G = 1u << args.log2g;
@@ -19,64 +26,72 @@ __device__ __forceinline__ void accumulate_item(const AccArgs& args, uint32_t pa
   const uint32_t per = (args.tiles + args.slices - 1) / args.slices;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   const uint32_t nw = kAccBlock / 64;
-  constexpr int kU = 8;  // tiles in flight per wave
-  {
-    const uint32_t r = part >> args.log2g, g = part & (G - 1);
-    for (uint32_t i = threadIdx.x; i < span; i += kAccBlock) acc[i] = 0;
-    __syncthreads();
-    const uint32_t t0 = slice * per, t1 = min(args.tiles, t0 + per);
-    // each wave takes kU tiles at a time, so every wave of the block shares
-    // even a short slice; lanes 0..kU-1 fetch the tiles' group bounds
-    for (uint32_t tb = t0 + wave * kU; tb < t1; tb += nw * kU) {
-      uint32_t lb = 0, le = 0;
-      if (lane < kU && tb + lane < t1) {
-        lb = args.desc[desc_index(r, g, G, args.tiles, tb + lane)];
-        le = args.desc[desc_index(r, g + 1, G, args.tiles, tb + lane)];
+  constexpr uint32_t kU = 16;              // tiles per wave round
+  constexpr uint32_t kLpt = 16;            // lanes per tile in one load
+  constexpr uint32_t kTpl = 64 / kLpt;     // tiles per load
+  constexpr uint32_t kLoads = kU / kTpl;   // loads per round
+  const uint32_t r = part >> args.log2g, g = part & (G - 1);
+  for (uint32_t i = threadIdx.x; i < span; i += kAccBlock) acc[i] = 0;
+  __syncthreads();
+  const uint32_t t0 = slice * per, t1 = min(args.tiles, t0 + per);
+  const uint32_t sub = lane / kLpt, li = lane % kLpt;
+  const uint4* const spare = (const uint4*)args.recs;
+  for (uint32_t tb = t0 + wave * kU; tb < t1; tb += nw * kU) {
+    // lanes 0..kU-1 fetch the group bounds of tiles tb + lane
+    uint32_t lb = 0, le = 0;
+    if (lane < kU && tb + lane < t1) {
+      lb = args.desc[desc_index(r, g, G, args.tiles, tb + lane)];
+      le = args.desc[desc_index(r, g + 1, G, args.tiles, tb + lane)];
+    }
+    uint32_t lo[kLoads], hi[kLoads];
+    const uint4* src[kLoads];
+#pragma unroll
+    for (uint32_t q = 0; q < kLoads; ++q) {
+      const uint32_t u = q * kTpl + sub;  // this lane's tile in load q
+      lo[q] = __shfl(lb, u, 64);
+      hi[q] = __shfl(le, u, 64);
+      src[q] = (const uint4*)(args.recs + ((size_t)(tb + u) * args.rows + r) * args.tile_keys);
+    }
+    for (uint32_t c = li;; c += kLpt) {  // chunk index from the group's first chunk
+      u32x4 v[kLoads];
+      uint32_t pos[kLoads];
+      bool more = false;
+#pragma unroll
+      for (uint32_t q = 0; q < kLoads; ++q) {
+        const uint32_t ch = (lo[q] >> 2) + c;
+        pos[q] = ch * 4;
+        const u32x4* at = (const u32x4*)(pos[q] < hi[q] ? src[q] + ch : spare);
+        v[q] = *at;
+        more |= pos[q] + 4 * kLpt < hi[q];
       }
-      const uint32_t ntiles = min((uint32_t)kU, t1 - tb);
-      uint32_t cur[kU], end[kU];
-      const uint32_t* src[kU];
+      // whole 16-byte loads, all issued before the first record is used (the
+      // compiler would otherwise move a word's load into the branch using it)
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        cur[u] = __shfl(lb, u, 64);
-        end[u] = (uint32_t)u < ntiles ? __shfl(le, u, 64) : cur[u];
-        src[u] = args.recs + ((size_t)(tb + u) * args.rows + r) * args.tile_keys;
-      }
-      bool more = true;
-      while (more) {
-        uint32_t v[kU];
-        bool has[kU];
+      for (uint32_t q = 0; q < kLoads; ++q) asm volatile("" : "+v"(v[q]));
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const uint32_t idx = cur[u] + lane;
-          has[u] = idx < end[u];
-          v[u] = has[u] ? src[u][idx] : 0u;
-        }
+      for (uint32_t q = 0; q < kLoads; ++q) {
+        const uint32_t w4[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
-        for (int u = 0; u < kU; ++u)
-          if (has[u]) {
-            const int64_t sw = (int64_t)((int32_t)(v[u] << (log2r + 1)) >> (log2r + 1));
-            atomicAdd(&acc[v[u] >> (wb + 1)], (unsigned long long)sw);
+        for (uint32_t e = 0; e < 4; ++e)
+          if (pos[q] + e >= lo[q] && pos[q] + e < hi[q]) {
+            const int64_t sw = (int64_t)((int32_t)(w4[e] << (log2r + 1)) >> (log2r + 1));
+            atomicAdd(&acc[w4[e] >> (wb + 1)], (unsigned long long)sw);
           }
-        more = false;
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          cur[u] += 64;
-          more |= cur[u] < end[u];
-        }
       }
+      if (!__any(more)) break;
     }
-    __syncthreads();
-    unsigned long long* dst = args.table + ((size_t)r << args.log2m) + ((size_t)g << log2r);
-    for (uint32_t i = threadIdx.x; i < span; i += kAccBlock) {
-      unsigned long long v = acc[i];
-      if (v) atomicAdd(&dst[i], v);
-    }
-    __syncthreads();
-    }
+  }
+  __syncthreads();
+  unsigned long long* dst = args.table + ((size_t)r << args.log2m) + ((size_t)g << log2r);
+  for (uint32_t i = threadIdx.x; i < span; i += kAccBlock) {
+    unsigned long long v = acc[i];
+    if (v) atomicAdd(&dst[i], v);
+  }
+  __syncthreads();
 }
 
-__global__ __launch_bounds__(kAccBlock) void k_accumulate(AccArgs args) {
+// two 16-wave blocks per CU (8 waves per SIMD): at most 64 VGPRs
+__global__ __launch_bounds__(kAccBlock, 8) void k_accumulate(AccArgs args) {
   extern __shared__ unsigned long long acc[];
   const uint32_t items = (args.rows << args.log2g) * args.slices;
   for (uint32_t item = blockIdx.x; item < items; item += gridDim.x)
@@ -217,7 +232,7 @@ __global__ void k_fill_zero(unsigned long long* __restrict__ dst, uint64_t n) {
     dst[i] = 0;
 }
 
-__global__ __launch_bounds__(kAccBlock) void k_batch_acc(const BatchSegment* __restrict__ segs,
+__global__ __launch_bounds__(kAccBlock, 8) void k_batch_acc(const BatchSegment* __restrict__ segs,
                                                         const BatchAccItem* __restrict__ items, uint32_t nitems) {
   extern __shared__ unsigned long long acc[];
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
