@@ -598,7 +598,11 @@ __device__ __forceinline__ void bin_rows_wave(const BA& args, uint32_t tile, uin
   static_assert(kUse <= kKpt, "more slots than the tile holds");
   const uint32_t log2r = args.log2r, wb = 31u - log2r;
   const uint32_t NC = 4 * G;  // counters per row: 2G real, 2G spare; NC <= 64
-  for (uint32_t r = 0; r < args.rows; ++r) {
+  // this lane's descriptor (group `lane` of the tile) in row 0; rows follow at
+  // a stride of (G + 1) * tiles words
+  uint32_t* dsc = args.desc + desc_index(0, lane, G, args.tiles, tile);
+  const size_t dstride = (size_t)(G + 1) * args.tiles;
+  for (uint32_t r = 0; r < args.rows; ++r, dsc += dstride) {
     const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
     uint32_t* const hrow = hist + r * NC;
     uint32_t code[kUse], gq[kUse], tick[kUse];
@@ -627,18 +631,20 @@ __device__ __forceinline__ void bin_rows_wave(const BA& args, uint32_t tile, uin
     v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);
     v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);
     v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);
-    if (NC > 16) {
+    if (NC > 32) {
       const uint32_t t0 = __builtin_amdgcn_readlane(v, 15);
       const uint32_t t1 = t0 + __builtin_amdgcn_readlane(v, 31);
       const uint32_t t2 = t1 + __builtin_amdgcn_readlane(v, 47);
       v += lane < 16 ? 0u : lane < 32 ? t0 : lane < 48 ? t1 : t2;
+    } else if (NC > 16) {
+      v += lane < 16 ? 0u : __builtin_amdgcn_readlane(v, 15);
     }
     // lane c: byte offset of counter c's records in the staging area; range g
     // starts at counter 2g, and counter 2G (the first spare) ends the records
     const uint32_t off = v - cg;
     const uint32_t nrec = __builtin_amdgcn_readlane(off, 2 * G) >> 2;
     const uint32_t goff = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(lane << 3), (int)off);
-    if (lane <= G) args.desc[desc_index(r, lane, G, args.tiles, tile)] = goff >> 2;
+    if (lane <= G) *dsc = goff >> 2;
     unsigned char* const stage_b = (unsigned char*)stage;
 #pragma unroll
     for (int j = 0; j < kUse; ++j) {
