@@ -160,6 +160,22 @@ __device__ __forceinline__ uint32_t bucket_code(const RowCoeffs<K, NP>& c, uint3
   }
 }
 
+// Bucket and sign mask (0 or all ones) of a key: from the code for the
+// low-bit split, where the code is the hash's low word, else directly.
+template <int PRIME, int MODE, int K, bool WIDE, int NP>
+__device__ __forceinline__ void bucket_mask(const RowCoeffs<K, NP>& c, uint32_t x0, uint32_t x1, uint32_t log2m,
+                                            uint32_t& bucket, uint32_t& m) {
+  if constexpr (MODE == kTwoForOne) {
+    const uint32_t code = bucket_code<PRIME, MODE, K, WIDE, NP>(c, x0, x1, log2m);
+    bucket = __builtin_amdgcn_ubfe(code, 1u, log2m);
+    m = (uint32_t)__builtin_amdgcn_sbfe((int)code, 0, 1);
+  } else {
+    uint32_t a;
+    bucket_sign<PRIME, MODE, K, WIDE, NP>(c, x0, x1, log2m, bucket, a);
+    m = 0u - a;
+  }
+}
+
 template <typename KeyT>
 __device__ __forceinline__ void load_key(const KeyT* __restrict__ keys, uint64_t i, uint32_t& x0, uint32_t& x1) {
   if constexpr (sizeof(KeyT) == 4) {
@@ -215,6 +231,15 @@ __device__ __forceinline__ unsigned long long signed_weight(int64_t w, uint32_t 
   return (unsigned long long)(a ? -w : w);
 }
 
+// s*w for a sign mask m (0 for s = 1, all ones for s = -1), given w and
+// wd = w ^ -w: w ^ (wd & m).
+__device__ __forceinline__ unsigned long long masked_signed(uint32_t m, int64_t w, uint64_t wd) {
+  const uint64_t wp = (uint64_t)w;
+  const uint32_t lo = (uint32_t)wp ^ ((uint32_t)wd & m);
+  const uint32_t hi = (uint32_t)(wp >> 32) ^ ((uint32_t)(wd >> 32) & m);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 // ---------------------------------------------------------------------------
 // Single pass with the whole table in LDS.  Each block zeroes its private
 // table, processes a contiguous key range, then adds the non-zero partial
@@ -244,22 +269,26 @@ __device__ __forceinline__ void lds_block_update(const UpdateArgs<KeyT, WT>& arg
     if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;  // key >= 2^60 breaks p >= 2u - 1
     // wave-uniform choice of the one-limb key path (all keys < 2^32)
     const bool wide = PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0);
+    // w ^ -w of each weight, so a row applies the sign with bit operations
+    uint64_t wneg[kKpt];
+#pragma unroll
+    for (int j = 0; j < kKpt; ++j) wneg[j] = (uint64_t)wv[j] ^ (uint64_t)(-wv[j]);
     for (uint32_t r = 0; r < args.rows; ++r) {
       const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
       unsigned long long* row = lds + ((size_t)r << args.log2m);
       if (wide) {
 #pragma unroll
         for (int j = 0; j < kKpt; ++j) {
-          uint32_t bk, a;
-          bucket_sign<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m, bk, a);
-          if (ok[j]) atomicAdd(&row[bk], signed_weight(wv[j], a));
+          uint32_t bk, m;
+          bucket_mask<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m, bk, m);
+          if (ok[j]) atomicAdd(&row[bk], masked_signed(m, wv[j], wneg[j]));
         }
       } else {
 #pragma unroll
         for (int j = 0; j < kKpt; ++j) {
-          uint32_t bk, a;
-          bucket_sign<PRIME, MODE, K, false, NP>(c, x0[j], x1[j], args.log2m, bk, a);
-          if (ok[j]) atomicAdd(&row[bk], signed_weight(wv[j], a));
+          uint32_t bk, m;
+          bucket_mask<PRIME, MODE, K, false, NP>(c, x0[j], x1[j], args.log2m, bk, m);
+          if (ok[j]) atomicAdd(&row[bk], masked_signed(m, wv[j], wneg[j]));
         }
       }
     }
