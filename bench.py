@@ -19,7 +19,7 @@ Other workloads (--workload) measure the other kernels the same way:
   batched                      4096 sketches (t=5, m=2^e, e uniform in 8..16, seeds 4000+i), stream
                                lengths floor(2^U(8,22)), uint64 Zipf(1.1) keys, int32 weights in
                                [-100,100]: one batched update (autotuned, HIP graph) vs 4096 cs_update
-Prints one JSON line.  --gpus N > 1 exits: this build measures one GPU.
+Prints one JSON line.  --gpus N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -643,8 +643,9 @@ def main():
     ap.add_argument("--no-naive", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build measures one GPU "
-              f"(the sketch shards by key range plus one int64 all-reduce, not built here)", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported; the benchmark runs on one GPU "
+              f"(the sketch would shard by key range plus one int64 all-reduce, which is not implemented)",
+              file=sys.stderr)
         sys.exit(2)
     if args.calib_copy:
         import torch
