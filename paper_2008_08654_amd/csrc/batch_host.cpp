@@ -45,16 +45,17 @@ constexpr uint32_t kMaxLdsTable = 160 * 1024;
 constexpr uint32_t kDefaultChunk = 1u << 16;
 constexpr uint32_t kGlobalChunk = kBlock * kKeysPerThread;  // one pass of a block: spreads short streams over CUs
 constexpr double kDefaultDirect = 0.125;
+constexpr uint32_t kBatchRangeLog2 = 13;
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 }  // namespace
 
-// Range width of the two-pass update in a batch: the widest range pass 2 can
-// hold in LDS (fewest partitions, so the most records per tile and partition);
-// the batch's many segments supply the parallelism.  Wave tiles take at most
-// 16 ranges per row.
+// Range width of the two-pass update in a batch: 2^13 counters (a 64 KiB
+// pass-2 table, two 16-wave blocks per CU; 2^14 halves that occupancy and
+// measured 11% slower on the 4096-sketch batch), wider only where a row would
+// otherwise need more than the 16 ranges wave tiles take.
 bool mcs::batch_twopass_shape(uint32_t rows, uint32_t log2m, uint32_t* log2g, uint32_t* log2r) {
   if (log2m > 18 || rows > 16) return false;
-  const uint32_t lr = std::min(log2m, kMaxRangeLog2);
+  const uint32_t lr = std::min(log2m, std::max(kBatchRangeLog2, log2m > 4 ? log2m - 4 : 0u));
   *log2r = lr;
   *log2g = log2m - lr;
   return (1u << *log2g) <= 16;
