@@ -370,19 +370,24 @@ __global__ __launch_bounds__(kBlock) void k_update_global(UpdateArgs<KeyT, WT> a
 // add the non-zero counters into the global table with coalesced atomics.
 // ---------------------------------------------------------------------------
 
-// Exclusive prefix of in[0..G) into out[0..G] by one wave (out[G] = total).
+// Exclusive prefix of in[0..G) into out[0..G] by one wave (out[G] = total):
+// per 64 entries, DPP within 16-lane rows (row_shr 1, 2, 4, 8), then each
+// row adds the totals of the rows before it.
 __device__ __forceinline__ void wave_exclusive_scan(const uint32_t* in, uint32_t* out, uint32_t G, uint32_t lane) {
   uint32_t carry = 0;
   for (uint32_t b = 0; b < G; b += 64) {
     const uint32_t v0 = b + lane < G ? in[b + lane] : 0u;
     uint32_t v = v0;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      uint32_t t = __shfl_up(v, d, 64);
-      if (lane >= (uint32_t)d) v += t;
-    }
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);
+    const uint32_t t0 = __builtin_amdgcn_readlane(v, 15);
+    const uint32_t t1 = t0 + __builtin_amdgcn_readlane(v, 31);
+    const uint32_t t2 = t1 + __builtin_amdgcn_readlane(v, 47);
+    v += lane < 16 ? 0u : lane < 32 ? t0 : lane < 48 ? t1 : t2;
     if (b + lane < G) out[b + lane] = carry + v - v0;
-    carry += __shfl(v, 63, 64);
+    carry += __builtin_amdgcn_readlane(v, 63);
   }
   if (lane == 0) out[G] = carry;
 }
