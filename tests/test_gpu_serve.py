@@ -99,7 +99,7 @@ def test_served_mixed_and_alone_match_oracle():
 
 def test_served_f2_sees_exactly_the_earlier_updates():
     """Update, F2, update, F2 on one tenant, queued at once (one step would hold them
-    all if the ordering rule did not close it)."""
+    all if the ordering rule did not hold the second update back)."""
     srv = M.Server()
     t = srv.admit(5, 1 << 12, 77)
     keys = W.zipf(5, 30000, 1.2, 1 << 32).to(DEV)
@@ -146,6 +146,35 @@ def test_served_admission_budget_and_eviction():
         srv.admit(4, 1 << 19, 3)    # more buckets than the batched update takes
     with pytest.raises(M.MCSError):
         M.Server(hbm_budget=own - 1, work_bytes=work)
+    srv.close()
+
+
+def test_held_back_tenant_does_not_close_the_step():
+    """F2(a), update(a), update(b), F2(b), F2(a) queued at once: a's update waits for a
+    later step (a's first F2 must not see it) and so does a's second F2, while b's
+    requests still join the first step; every answer is the oracle's for exactly the
+    updates submitted before it."""
+    srv = M.Server(step_keys=1 << 22)
+    a, b = srv.admit(3, 1 << 10, 41), srv.admit(4, 1 << 12, 42)
+    keys = W.zipf(11, 20000, 1.2, 1 << 32).to(DEV)
+    w = W.bounded_int(11, 20000, -100, 100).to(torch.int32).to(DEV)
+    ka, wa, kb, wb = keys[:8000], w[:8000], keys[8000:], w[8000:]
+    trace = [(a, M.CS_REQ_F2, None, None), (a, M.CS_REQ_UPDATE, ka, wa), (b, M.CS_REQ_UPDATE, kb, wb),
+             (b, M.CS_REQ_F2, None, None), (a, M.CS_REQ_F2, None, None)]
+    res = srv.replay(trace, np.zeros(len(trace)))
+    assert all(r.status == M.CS_OK for r in res)
+
+    def f2_after(rows, log2m, seed, k, ww):
+        table = O.cs_update(O.PRIME_P61, O.TWO_FOR_ONE, rows, 1 << log2m,
+                            O.coeffs_from_seed(O.PRIME_P61, rows, O.TWO_FOR_ONE, seed), W.as_uint64_numpy(k),
+                            ww.cpu().numpy().astype(np.int64))
+        return O.cs_estimate_status(table)[1]
+
+    assert res[0].f2 == 0  # nothing of a's was submitted before it
+    assert res[3].f2 == f2_after(4, 12, 42, kb, wb)
+    assert res[4].f2 == f2_after(3, 10, 41, ka, wa)
+    assert res[2].step == res[3].step == res[0].step  # b joined the step a's update was held from
+    assert res[1].step > res[0].step and res[4].step >= res[1].step
     srv.close()
 
 
