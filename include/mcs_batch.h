@@ -57,9 +57,10 @@ cs_status cs_batch_create(const cs_batch_item* items, uint32_t count, cs_dtype k
 /* Enqueues one update of every member on `stream` (adds each stream into its
  * sketch, as cs_update would). */
 cs_status cs_batch_update(cs_batch* b, hipStream_t stream);
-/* Tries candidate options (LDS table limit, LDS chunk, combining, direct
- * fraction 1/128, 1/8 or 1) on the real batch, keeps the fastest and writes it
- * to *chosen (may be NULL).  The trial runs add into the members' tables:
+/* Tries candidate options (LDS table limit 8 (no table in LDS), 20480, 40960,
+ * 65536 or 163840 bytes; LDS chunk 2^15 or 2^17 keys; combining on or off;
+ * direct fraction 1/128, 1/8 or 1) on the real batch, keeps the fastest and
+ * writes it to *chosen (may be NULL).  The trial runs add into the members' tables:
  * they are zeroed (cs_reset) when it returns.  Synchronises `stream`. */
 cs_status cs_batch_autotune(cs_batch* b, hipStream_t stream, cs_batch_options* chosen);
 cs_status cs_batch_get_options(const cs_batch* b, cs_batch_options* out);

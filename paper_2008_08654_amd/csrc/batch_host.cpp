@@ -370,7 +370,9 @@ extern "C" cs_status cs_batch_autotune(cs_batch* b, hipStream_t stream, cs_batch
   if (!b) return fail(CS_EINVAL, "batch is NULL");
   const cs_batch_options keep = b->opts;
   std::vector<cs_batch_options> cands;
-  for (uint32_t lm : {40960u, 65536u, 163840u})
+  // LDS limits from "no table in LDS" (8 bytes: repeated keys then meet the
+  // two-pass update's combining) to the largest table LDS holds
+  for (uint32_t lm : {8u, 20480u, 40960u, 65536u, 163840u})
     for (uint32_t ch : {1u << 15, 1u << 17})
       for (int cb : {1, -1})
         for (double df : {1.0 / 128, 0.125, 1.0}) cands.push_back(cs_batch_options{lm, ch, cb, keep.use_graph, df});
