@@ -128,7 +128,8 @@ def _stream_ptr(torch):
 
 def cpu_baseline_sketch(keys_dev, w_dev, wl, budget_s=15.0):
     """Times the oracle (the plain CPU implementation, as it stands) on a bounded
-    prefix of the same stream, one thread per row."""
+    prefix of the same stream, one thread per row.  Returns the baseline record,
+    the oracle's table for that prefix and the prefix length."""
     import numpy as np
     import oracle as O
     rows, m, mode = wl["rows"], wl.get("buckets", 1 << wl["log2m"]), wl["mode"]
@@ -153,10 +154,28 @@ def cpu_baseline_sketch(keys_dev, w_dev, wl, budget_s=15.0):
     k = host(keys_dev, n)
     w = w_dev[:n].cpu().numpy().astype(np.int64)
     t0 = time.perf_counter()
-    O.cs_update(prime, mode, rows, m, coeffs, k, w)
+    table = O.cs_update(prime, mode, rows, m, coeffs, k, w)
     dt = time.perf_counter() - t0
-    return {"value": round(n / dt / 1e9, 6), "unit": "Gkeys/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} keys of the same stream, same sketch; {dt:.1f} s; one thread per row"}
+    rec = {"value": round(n / dt / 1e9, 6), "unit": "Gkeys/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {n} keys of the same stream, same sketch; {dt:.1f} s; one thread per row"}
+    return rec, table, n
+
+
+def sketch_parity(sk, table, n_checked, n_total):
+    """Bit-exact comparison of the sketch's counters, row estimates and median with the
+    oracle's table (every counter, every row value)."""
+    import numpy as np
+    import oracle as O
+    got = sk.counters()
+    st, f2, rows = sk.estimate_f2_status()
+    wst, wmed, wrows = O.cs_estimate_status(table)
+    diff = int((got != table).sum())
+    ok = diff == 0 and list(rows) == list(wrows) and f2 == wmed and (st == 0) == (wst == 0)
+    what = "all" if n_checked == n_total else f"the first {n_checked} of the"
+    return {"status": "bit-exact" if ok else "MISMATCH",
+            "checked": f"counters ({table.size}), {len(wrows)} row estimates and the median over {what} "
+                       f"{n_total} keys against the oracle",
+            "counters_differing": diff}
 
 
 def run_sketch(args, wl):
@@ -234,7 +253,20 @@ def run_sketch(args, wl):
                         "algorithmic_ops_per_key": ops_key,
                         "hbm_frac_of_input_stream": round(bytes_key * n / (upd_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_sketch(keys, w, wl)
+        out["cpu_baseline"], table, n_or = cpu_baseline_sketch(keys, w, wl)
+        # Parity on the benchmark's own inputs: the timed steps reset the counters and
+        # add the whole stream, so the table now holds one update of all n keys.  A
+        # prefix-only oracle run is checked on a fresh sketch updated with that prefix.
+        if n_or == n:
+            out["parity"] = sketch_parity(sk, table, n_or, n)
+        else:
+            chk = M.Sketch(rows, m, prime=prime, seed=wl["seed"], mode=mode)
+            M._check(L.cs_update(chk.handle, kp, kt, wp, wt, n_or, stream))
+            out["parity"] = sketch_parity(chk, table, n_or, n)
+            chk.close()
+        del table
+    else:
+        out["parity"] = {"status": "not checked (--no-cpu-baseline)"}
     sk.close()
     return out
 
@@ -330,21 +362,39 @@ def run_batched(args):
                         "algorithmic_ops_per_key": ops_key}}
     if not args.no_cpu_baseline:
         import oracle as O
+        # Parity on the benchmark's own inputs: the tables are cleared and take exactly one
+        # batched update; every member the oracle sample reaches is then compared with the
+        # oracle's table for its stream, counter by counter.
+        for sk in sketches:
+            sk.reset(stream)
+        batch.update(stream)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
+        t_or = 0.0
         done = 0
         i = 0
-        while time.perf_counter() - t0 < 15.0 and i < count:
+        bad_members, by_class = [], {}
+        while t_or < 15.0 and i < count:
             sk, k, ww = members[i]
-            if k.numel():
-                c = O.coeffs_from_seed(O.PRIME_P61, 5, O.TWO_FOR_ONE, 4000 + i)
-                O.cs_update(O.PRIME_P61, O.TWO_FOR_ONE, 5, 1 << int(log2m[i]), c, k.cpu().numpy().view(np.uint64),
-                            ww.cpu().numpy().astype(np.int64))
-                done += k.numel()
+            c = O.coeffs_from_seed(O.PRIME_P61, 5, O.TWO_FOR_ONE, 4000 + i)
+            kh, wh = k.cpu().numpy().view(np.uint64), ww.cpu().numpy().astype(np.int64)
+            t1 = time.perf_counter()
+            want = O.cs_update(O.PRIME_P61, O.TWO_FOR_ONE, 5, 1 << int(log2m[i]), c, kh, wh)
+            t_or += time.perf_counter() - t1
+            done += k.numel()
+            if not np.array_equal(sk.counters(), want):
+                bad_members.append(i)
             i += 1
-        dt = time.perf_counter() - t0
-        _log(f"batched: oracle sample of {i} members done")
-        out["cpu_baseline"] = {"value": round(done / dt / 1e9, 6), "unit": "Gkeys/s", "cores": 5, "kind": "oracle",
-                               "sample": f"first {i} members ({done} keys), {dt:.1f} s, one thread per row"}
+        _log(f"batched: oracle sample of {i} members done, {len(bad_members)} differ")
+        out["cpu_baseline"] = {"value": round(done / t_or / 1e9, 6), "unit": "Gkeys/s", "cores": 5,
+                               "kind": "oracle",
+                               "sample": f"first {i} members ({done} keys), {t_or:.1f} s, one thread per row"}
+        out["parity"] = {"status": "bit-exact" if not bad_members else "MISMATCH",
+                         "checked": f"every counter of the first {i} of {count} members ({done} of {total} keys) "
+                                    f"after one batched update, against the oracle",
+                         "members_differing": bad_members[:16]}
+    else:
+        out["parity"] = {"status": "not checked (--no-cpu-baseline)"}
     for sk in sketches:
         sk.close()
     batch.close()
@@ -425,6 +475,35 @@ def run_served(args):
                         "kernel": "served steps (all launches, closed loop)", "algorithmic_ops_per_key": ops_key}}
     if not args.no_cpu_baseline:
         import oracle as O
+        # Parity on the benchmark's own inputs: the warm-up replay ran the first n_req / 20
+        # requests and four replays ran all of them, so a tenant's counters must equal the
+        # oracle's table of its updates in the prefix plus four times that of all its updates.
+        upd_of = {}
+        for i, (t, f) in enumerate(zip(tenant.tolist(), is_f2.tolist())):
+            if not f and int(size[i]):
+                upd_of.setdefault(t, []).append(i)
+        sample = sorted(upd_of)[:: max(1, len(upd_of) // 8)][:8]
+        bad_tenants = []
+        checked_keys = 0
+        for t in sample:
+            c = O.coeffs_from_seed(O.PRIME_P61, rows, O.TWO_FOR_ONE, 5000 + t)
+            m_t = 1 << log2m[t]
+            prefix = np.zeros((rows, m_t), dtype=np.int64)
+            full = np.zeros((rows, m_t), dtype=np.int64)
+            for i in upd_of[t]:
+                n_i, o_i = int(size[i]), offs[i]
+                kh, wh = W.as_uint64_numpy(keys[o_i:o_i + n_i]), w[o_i:o_i + n_i].cpu().numpy().astype(np.int64)
+                O.cs_update(O.PRIME_P61, O.TWO_FOR_ONE, rows, m_t, c, kh, wh, table=full)
+                if i < n_req // 20:
+                    O.cs_update(O.PRIME_P61, O.TWO_FOR_ONE, rows, m_t, c, kh, wh, table=prefix)
+                checked_keys += n_i
+            if not np.array_equal(srv.counters(ids[t], rows, m_t), prefix + 4 * full):
+                bad_tenants.append(t)
+        out["parity"] = {"status": "bit-exact" if not bad_tenants and not bad else "MISMATCH",
+                         "checked": f"every counter of tenants {sample} ({checked_keys} update keys per replay) "
+                                    f"after all replays, against the oracle; failed requests: {bad}",
+                         "tenants_differing": bad_tenants}
+        _log(f"served: parity over {len(sample)} tenants: {out['parity']['status']}")
         coeffs = {}
         t0 = time.perf_counter()
         done = 0
@@ -443,6 +522,8 @@ def run_served(args):
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": round(done / dt / 1e9, 6), "unit": "Gkeys/s", "cores": rows, "kind": "oracle",
                                "sample": f"first {i} requests ({done} keys), {dt:.1f} s, one thread per row"}
+    else:
+        out["parity"] = {"status": "not checked (--no-cpu-baseline)"}
     srv.close()
     return out
 
@@ -666,6 +747,15 @@ def main():
         out = run_sketch(args, SKETCH_WORKLOADS[args.workload])
     else:
         out = run_divmod(args, DIVMOD_WORKLOADS[args.workload])
+    # A run whose work failed or disagreed with the oracle reports no throughput.
+    failed = out.get("config", {}).get("failed_requests", 0) or out.get("config", {}).get("failed_members", 0)
+    mismatch = str(out.get("parity", {}).get("status", "")).startswith("MISMATCH")
+    if failed or mismatch:
+        out["value"] = None
+        print(json.dumps(out), flush=True)
+        print(f"bench.py: {'failed work' if failed else 'parity mismatch'}: no throughput is reported",
+              file=sys.stderr, flush=True)
+        sys.exit(1)
     print(json.dumps(out), flush=True)
 
 

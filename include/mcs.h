@@ -101,9 +101,10 @@ void cs_destroy(cs_sketch* s);
  * the next synchronising call (cs_estimate_f2, cs_read_counters, cs_sync)
  * returns; the counters are then meaningless.  n = 0 is a no-op.
  * The work is enqueued on `stream` (0 = default stream) and the call returns
- * without waiting.  Updates on one sketch must not run concurrently on
- * different streams unless the caller orders them (addition commutes, so
- * the result would still be exact, but cs_reset/reads would race).
+ * without waiting.  Every call on a sketch (update, reset, merge, estimate,
+ * reads) must be ordered with the others, for example by issuing them all on
+ * one stream: calls on different streams that overlap in time race on the
+ * counters and on the update's workspace, and give undefined counters.
  * ------------------------------------------------------------------------- */
 cs_status cs_update(cs_sketch* s, const void* keys, cs_dtype key_type, const void* weights,
                     cs_dtype weight_type, uint64_t n, hipStream_t stream);
@@ -125,13 +126,16 @@ cs_status cs_query(cs_sketch* s, const void* keys, cs_dtype key_type, uint64_t n
                    hipStream_t stream);
 
 /* Update paths.  AUTO picks LDS when the whole table (rows*buckets*8 bytes)
- * fits in 64 KiB, else BINNED (two passes through a library-owned workspace),
- * else GLOBAL (one device-scope atomic per key and row).  BINNED first
- * combines repeated keys within each tile of 2048 keys (the sketch is linear,
- * so C[i(x)] += s(x) * (sum of their weights) is the same update);
- * BINNED_NOCOMBINE skips that step.  All paths give identical counters;
- * forcing one is for testing and tuning. */
-enum { CS_PATH_AUTO = 0, CS_PATH_LDS = 1, CS_PATH_GLOBAL = 2, CS_PATH_BINNED = 3, CS_PATH_BINNED_NOCOMBINE = 4 };
+ * fits in 64 KiB; else ROWS when a row has at most 2^16 buckets (each block
+ * holds the rows of one row group in LDS as 16-bit fields, whose rare wraps
+ * are carried into the int64 table exactly); else BINNED (two passes through
+ * a library-owned workspace); else GLOBAL (one device-scope atomic per key and
+ * row).  BINNED first combines repeated keys within each tile of keys (the
+ * sketch is linear, so C[i(x)] += s(x) * (sum of their weights) is the same
+ * update); BINNED_NOCOMBINE skips that step.  All paths give identical
+ * counters; forcing one is for testing and tuning. */
+enum { CS_PATH_AUTO = 0, CS_PATH_LDS = 1, CS_PATH_GLOBAL = 2, CS_PATH_BINNED = 3, CS_PATH_BINNED_NOCOMBINE = 4,
+       CS_PATH_ROWS = 5 };
 cs_status cs_set_update_path(cs_sketch* s, int path);
 
 /* Copies the rows*buckets counters (row-major, no padding) to host memory;
@@ -213,6 +217,12 @@ cs_status mersenne_divmod_wide(uint32_t b, uint32_t c, int method, const uint32_
 /* Synchronises `stream` and returns (and clears) the domain flag of the
  * quotient/remainder calls on the current device. */
 cs_status mersenne_status(hipStream_t stream);
+
+/* The status the library reports for a HIP runtime error code (a hipError_t
+ * value): CS_OK for success, CS_ENOMEM for an out-of-memory error, CS_EDEVICE
+ * for every other error (for example a fault left behind by an earlier kernel,
+ * which later runtime calls keep returning).  Needs no device. */
+cs_status cs_status_from_hip_error(int hip_error);
 
 /* Message for the last error on the calling thread ("" if none). */
 const char* cs_last_error(void);

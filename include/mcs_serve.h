@@ -16,7 +16,11 @@
  * Requests of different tenants are not ordered with respect to each other.
  *
  * Key and weight buffers of an update are caller-owned device memory and
- * must stay valid and unchanged until the update's ticket completes.
+ * must stay valid and unchanged until the update's ticket completes.  The
+ * server reads them on a stream of its own, which is not ordered with the
+ * caller's streams: their contents must be complete when the update is
+ * submitted (a caller that fills them asynchronously synchronises that work,
+ * for example its stream, before submitting).
  * All calls are thread-safe.
  */
 #ifndef MCS_SERVE_H

@@ -25,7 +25,7 @@ CS_TWO_FOR_ONE, CS_TWO_FOR_ONE_MSB, CS_TWO_POLY, CS_ARB_R = 0, 1, 2, 3
 CS_MAP_EXACT, CS_MAP_MERSENNE = 0, 1
 CS_WIDE_ALG5, CS_WIDE_CCH = 0, 1
 CS_U32, CS_U64, CS_I32, CS_I64 = 0, 1, 2, 3
-CS_PATH_AUTO, CS_PATH_LDS, CS_PATH_GLOBAL, CS_PATH_BINNED, CS_PATH_BINNED_NOCOMBINE = 0, 1, 2, 3, 4
+CS_PATH_AUTO, CS_PATH_LDS, CS_PATH_GLOBAL, CS_PATH_BINNED, CS_PATH_BINNED_NOCOMBINE, CS_PATH_ROWS = 0, 1, 2, 3, 4, 5
 
 _STATUS_NAMES = {0: "CS_OK", -1: "CS_EINVAL", -2: "CS_ENOMEM", -3: "CS_EDOMAIN", -4: "CS_EOVERFLOW",
                  -5: "CS_EDEVICE", -6: "CS_EBUSY"}
@@ -84,6 +84,7 @@ def lib() -> ctypes.CDLL:
             "cs_server_read_counters": [P, u32, P],
             "cs_server_get_stats": [P, P],
             "cs_server_replay": [P, P, u32, P, P],
+            "cs_status_from_hip_error": [i32],
         }
         for name, args in sig.items():
             f = getattr(L, name)

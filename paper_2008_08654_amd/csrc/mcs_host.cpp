@@ -32,9 +32,17 @@ cs_status mcs::fail(cs_status st, const char* fmt, ...) {
   return st;
 }
 
-cs_status mcs::hip_fail(hipError_t e, const char* what) {
-  return fail(CS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+cs_status mcs::status_of(hipError_t e) {
+  if (e == hipSuccess) return CS_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return CS_ENOMEM;
+  return CS_EDEVICE;
 }
+
+cs_status mcs::hip_fail(hipError_t e, const char* what) {
+  return fail(status_of(e) == CS_ENOMEM ? CS_ENOMEM : CS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" cs_status cs_status_from_hip_error(int hip_error) { return status_of((hipError_t)hip_error); }
 
 #define HIP_TRY(call)                                       \
   do {                                                      \
@@ -289,6 +297,16 @@ static bool binned_fits(const cs_sketch* s, uint32_t* log2g, uint32_t* log2r) {
   return true;
 }
 
+// Rows per row group of the row-resident update: the largest divisor of rows
+// whose 16-bit fields fit the block's LDS (0 if not even one row fits).
+static uint32_t rows_per_group(uint32_t rows, uint32_t log2m) {
+  if (log2m > kRowMaxLog2m) return 0;
+  const uint32_t fit = (uint32_t)(kRowLdsBytes / (2ull << log2m));
+  for (uint32_t r = std::min(rows, fit); r >= 1; --r)
+    if (rows % r == 0) return r;
+  return 0;
+}
+
 UpdatePlan mcs::plan_update(const cs_sketch* s, uint64_t n) {
   const DeviceInfo& dev = device_info(s->device);
   const uint64_t cells = (uint64_t)s->rows << s->log2m;
@@ -296,12 +314,24 @@ UpdatePlan mcs::plan_update(const cs_sketch* s, uint64_t n) {
   const uint64_t tiles = (n + tile - 1) / tile;
   UpdatePlan p{};
   uint32_t log2g = 0, log2r = 0;
+  const uint32_t rpg = rows_per_group(s->rows, s->log2m);
   int path = s->path;
   if (path == 0)
-    path = cells * 8 <= kLdsTableMax ? CS_PATH_LDS : binned_fits(s, &log2g, &log2r) ? CS_PATH_BINNED : CS_PATH_GLOBAL;
+    path = cells * 8 <= kLdsTableMax ? CS_PATH_LDS
+           : binned_fits(s, &log2g, &log2r) ? CS_PATH_BINNED
+                                            : CS_PATH_GLOBAL;
   if (path == CS_PATH_LDS && cells * 8 > kLdsTableMax) path = CS_PATH_GLOBAL;
+  if (path == CS_PATH_ROWS && !rpg) path = CS_PATH_GLOBAL;
   if (path == CS_PATH_BINNED && !binned_fits(s, &log2g, &log2r)) path = CS_PATH_GLOBAL;
-  if (path == CS_PATH_LDS) {
+  if (path == CS_PATH_ROWS) {
+    p.variant = kVariantRows;
+    p.rpg = rpg;
+    p.lds_bytes = (uint32_t)(rpg * (2ull << s->log2m));
+    const uint64_t groups = s->rows / rpg;
+    const uint64_t rtiles = (n + kRowTile - 1) / kRowTile;
+    p.tiles = (uint32_t)std::min<uint64_t>(rtiles, 0xffffffffull);
+    p.blocks = (uint32_t)std::max<uint64_t>(groups, std::min<uint64_t>((uint64_t)dev.cus, groups * rtiles));
+  } else if (path == CS_PATH_LDS) {
     p.variant = kVariantLds;
     p.lds_bytes = (uint32_t)(cells * 8);
     uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, kLdsPerCu / p.lds_bytes));
@@ -349,6 +379,7 @@ extern "C" cs_status cs_update(cs_sketch* s, const void* keys, cs_dtype key_type
   if (st != CS_OK) return st;
   if (n == 0) return CS_OK;
   if (!keys || !weights) return fail(CS_EINVAL, "keys or weights is NULL");
+  if (n > kMaxUpdateKeys) return fail(CS_EINVAL, "at most 2^40 keys per call");
   UpdatePlan plan = plan_update(s, n);
   return enqueue_update(s, plan, keys, kb, weights, wb, n, stream);
 }
@@ -359,7 +390,9 @@ static cs_status ensure_workspace(cs_sketch* s, size_t bytes) {
   hipError_t e = hipMalloc(&s->d_work, bytes);
   if (e != hipSuccess) {
     s->d_work = nullptr;
-    return fail(CS_ENOMEM, "update workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+    // out of memory is CS_ENOMEM; any other error (a fault an earlier kernel left
+    // behind, which every later runtime call returns) is CS_EDEVICE
+    return fail(status_of(e), "update workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
   }
   s->work_bytes = bytes;
   return CS_OK;
@@ -411,10 +444,15 @@ cs_status mcs::enqueue_update(cs_sketch* s, const UpdatePlan& plan, const void* 
     }
     return CS_OK;
   }
-  const uint64_t tile = (uint64_t)kBlock * kKeysPerThread;
   a.keys = keys;
   a.weights = weights;
   a.n = n;
+  if (plan.variant == kVariantRows) {
+    hipError_t e = launch_update(plan, a, stream);
+    if (e != hipSuccess) return hip_fail(e, "cs_update launch");
+    return CS_OK;
+  }
+  const uint64_t tile = (uint64_t)kBlock * kKeysPerThread;
   uint64_t per = (n + plan.blocks - 1) / plan.blocks;
   a.keys_per_block = (per + tile - 1) / tile * tile;
   UpdatePlan p = plan;
@@ -426,7 +464,7 @@ cs_status mcs::enqueue_update(cs_sketch* s, const UpdatePlan& plan, const void* 
 
 extern "C" cs_status cs_set_update_path(cs_sketch* s, int path) {
   if (!s) return fail(CS_EINVAL, "sketch is NULL");
-  if (path < CS_PATH_AUTO || path > CS_PATH_BINNED_NOCOMBINE) return fail(CS_EINVAL, "unknown update path %d", path);
+  if (path < CS_PATH_AUTO || path > CS_PATH_ROWS) return fail(CS_EINVAL, "unknown update path %d", path);
   s->path = path == CS_PATH_BINNED_NOCOMBINE ? CS_PATH_BINNED : path;
   s->combine = path != CS_PATH_BINNED_NOCOMBINE;
   return CS_OK;

@@ -36,6 +36,7 @@ namespace mcs {
 constexpr uint64_t kLdsTableMax = 64 * 1024;   // tables up to this size use the LDS single pass
 constexpr uint64_t kLdsPerCu = 160 * 1024;
 constexpr uint64_t kBinChunkKeys = 1ull << 27;  // keys per pass-1/pass-2 round of the binned update
+constexpr uint64_t kMaxUpdateKeys = 1ull << 40;  // keys per cs_update call (tile counts fit 32 bits)
 
 struct DeviceInfo {
   bool valid = false;
@@ -45,6 +46,9 @@ struct DeviceInfo {
 
 const DeviceInfo& device_info(int dev);
 cs_status fail(cs_status st, const char* fmt, ...);
+// CS_OK, CS_ENOMEM for an out-of-memory error, else CS_EDEVICE.
+cs_status status_of(hipError_t e);
+// Sets the last-error message and returns status_of(e) (never CS_OK).
 cs_status hip_fail(hipError_t e, const char* what);
 
 UpdatePlan plan_update(const cs_sketch* s, uint64_t n);

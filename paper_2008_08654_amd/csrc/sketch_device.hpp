@@ -18,6 +18,7 @@
 // sketch_kernels.hip.
 #pragma once
 #include <algorithm>
+#include <atomic>
 
 #include "device_util.hpp"
 #include "sketch_kernels.hpp"
@@ -349,6 +350,143 @@ __global__ __launch_bounds__(kBlock) void k_update_global(UpdateArgs<KeyT, WT> a
   const uint64_t begin = (uint64_t)blockIdx.x * args.keys_per_block;
   const uint64_t end = min(args.n, begin + args.keys_per_block);
   global_block_update<PRIME, MODE, K, KeyT, WT>(args, begin, end);
+}
+
+// ---------------------------------------------------------------------------
+// Row-resident update for tables of up to 2^16 buckets per row (a row of
+// 16-bit fields is at most 128 KiB of LDS).
+//
+// A block holds the counters of one row group (rpg rows) as 16-bit fields,
+// two per 32-bit LDS word: bucket 2i in the low half of word i, bucket 2i+1 in
+// the high half, each holding its running sum plus 2^15.  The blocks of a
+// group split the key tiles among themselves and hash every key for the
+// group's rows only, so each (key, row) is hashed once (Algorithm 2, Process)
+// and nothing is written per key.  A tile is read once per group: from HBM by
+// the first group to reach it, from L2 or the last-level cache by the others.
+//
+// Every add is a 32-bit LDS atomic that returns the old word.  A field whose
+// biased value leaves [0, 2^16) wraps, and the add that wrapped it sees so in
+// the old word; it then adds what the fields lost to the global int64
+// counters with device-scope atomics: +-2^16 on its own bucket and, for a low
+// field, the carry c that went into the high half (-c on the high bucket,
+// +-2^16 more if that carry wrapped the high half out of the word).  A field
+// must drift 2^15 from its bias to wrap, so these adds are rare.  At the end
+// each block adds field - 2^15 of every non-zero field into the global
+// counters.  Every step is an integer add, so the counters are exact in any
+// order.  Weights with |w| >= 2^15 skip the fields and go to the global
+// counters directly.
+// ---------------------------------------------------------------------------
+template <int PRIME, int MODE, int K, int NP, bool WIDE, typename KeyT, typename WT>
+__device__ __forceinline__ void rows_tile(const RowArgs<KeyT, WT>& args, uint32_t r0, uint32_t* words,
+                                          const uint32_t (&x0)[kRowKpt], const uint32_t (&x1)[kRowKpt],
+                                          const int32_t (&wf)[kRowKpt], const int64_t (&wv)[kRowKpt],
+                                          const bool (&esc)[kRowKpt], bool any_esc) {
+  const uint32_t m = 1u << args.log2m;
+  const uint32_t amask = 2u * m - 4u;  // byte offset of a bucket's word in its row: code & amask
+  for (uint32_t r = 0; r < args.rpg; ++r) {
+    const uint32_t row = r0 + r;
+    const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)row * NP * K);
+    unsigned char* const rowb = (unsigned char*)words + (size_t)r * 2u * m;
+    uint32_t code[kRowKpt], old[kRowKpt], sh[kRowKpt];
+    int32_t sw[kRowKpt];
+#pragma unroll
+    for (int j = 0; j < kRowKpt; ++j) code[j] = bucket_code<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m);
+#pragma unroll
+    for (int j = 0; j < kRowKpt; ++j) {
+      // s * w with s = 1 - 2a, a = bit 0 of the code; the field's half is bit 0
+      // of the bucket (bit 1 of the code)
+      const int32_t sgn = __builtin_amdgcn_sbfe((int)code[j], 0, 1);
+      sw[j] = (wf[j] ^ sgn) - sgn;
+      sh[j] = (code[j] & 2u) << 3;
+      old[j] = atomicAdd((uint32_t*)(rowb + (code[j] & amask)), (uint32_t)sw[j] << sh[j]);
+    }
+    bool wr[kRowKpt];
+    bool any_wr = false;
+#pragma unroll
+    for (int j = 0; j < kRowKpt; ++j) {
+      const int32_t t = (int32_t)__builtin_amdgcn_ubfe(old[j], sh[j], 16u) + sw[j];
+      wr[j] = (uint32_t)t > 0xFFFFu;
+      any_wr |= wr[j];
+    }
+    unsigned long long* const grow = args.table + ((size_t)row << args.log2m);
+    if (__any(any_wr)) {
+#pragma unroll
+      for (int j = 0; j < kRowKpt; ++j)
+        if (wr[j]) {
+          const uint32_t bucket = (code[j] >> 1) & (m - 1u);
+          const int32_t t = (int32_t)__builtin_amdgcn_ubfe(old[j], sh[j], 16u) + sw[j];
+          const int32_t cw = t >> 16;  // -1 or +1: the field lost -cw * 2^16
+          atomicAdd(&grow[bucket], (unsigned long long)((long long)cw * 65536));
+          if (sh[j] == 0) {  // the low half's carry went into the high half
+            const int32_t e = ((int32_t)(old[j] >> 16) + cw) >> 16;  // -1, 0 or +1
+            atomicAdd(&grow[bucket + 1], (unsigned long long)((long long)e * 65536 - cw));
+          }
+        }
+    }
+    if (any_esc) {
+#pragma unroll
+      for (int j = 0; j < kRowKpt; ++j)
+        if (esc[j]) {
+          const uint32_t bucket = (code[j] >> 1) & (m - 1u);
+          atomicAdd(&grow[bucket], signed_weight(wv[j], code[j] & 1u));
+        }
+    }
+  }
+}
+
+template <int PRIME, int MODE, int K, typename KeyT, typename WT>
+__global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> args) {
+  extern __shared__ __align__(16) uint32_t words[];
+  constexpr int NP = MODE == kTwoPoly ? 2 : 1;
+  const uint32_t G = args.groups;
+  const uint32_t g = blockIdx.x % G, rank = blockIdx.x / G;
+  const uint32_t cnt = (gridDim.x - g + G - 1) / G;  // blocks of group g
+  const uint32_t r0 = g * args.rpg;
+  const uint32_t nwords = args.rpg << (args.log2m - 1);
+  for (uint32_t i = threadIdx.x; i < nwords; i += kRowBlock) words[i] = 0x80008000u;
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint32_t bad = 0;
+  for (uint32_t t = rank; t < args.tiles; t += cnt) {
+    // wave `wave` takes keys [base, base + 64 * kRowKpt) of the tile
+    const uint64_t base = (uint64_t)t * kRowTile + (uint64_t)wave * (64 * kRowKpt);
+    if (base >= args.n) continue;
+    uint32_t x0[kRowKpt], x1[kRowKpt];
+    int64_t wv[kRowKpt];
+    bool ok[kRowKpt];
+    load_tile<kRowKpt>(args.keys, args.weights, base, 64, lane, args.n, x0, x1, wv, ok);
+    uint32_t any_hi = 0;
+    int32_t wf[kRowKpt];
+    bool esc[kRowKpt];
+    bool any_e = false;
+#pragma unroll
+    for (int j = 0; j < kRowKpt; ++j) {
+      any_hi |= x1[j];
+      const bool fits = wv[j] > -32768 && wv[j] < 32768;
+      wf[j] = ok[j] && fits ? (int32_t)wv[j] : 0;  // positions past n add 0
+      esc[j] = ok[j] && !fits;
+      any_e |= esc[j];
+    }
+    if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;  // key >= 2^60 breaks p >= 2u - 1
+    const bool any_esc = __any(any_e);
+    if (PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0))
+      rows_tile<PRIME, MODE, K, NP, true>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
+    else
+      rows_tile<PRIME, MODE, K, NP, false>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
+  }
+  if (bad) atomicOr(args.flags, kFlagDomain);
+  __syncthreads();
+  // add field - 2^15 of every non-zero field into the global counters; word i
+  // holds buckets 2i and 2i + 1 of its row, so a wave's adds are contiguous
+  const uint32_t lw = args.log2m - 1;
+  for (uint32_t i = threadIdx.x; i < nwords; i += kRowBlock) {
+    const uint32_t w = words[i];
+    const uint32_t r = i >> lw, wi = i & ((1u << lw) - 1u);
+    unsigned long long* const p = args.table + ((size_t)(r0 + r) << args.log2m) + 2u * wi;
+    const int32_t lo = (int32_t)(w & 0xFFFFu) - 32768, hi = (int32_t)(w >> 16) - 32768;
+    if (lo) atomicAdd(p, (unsigned long long)(long long)lo);
+    if (hi) atomicAdd(p + 1, (unsigned long long)(long long)hi);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1033,13 +1171,16 @@ hipError_t launch_update_t(const UpdatePlan& plan, const UpdateArgs<KeyT, WT>& a
   if (plan.variant == kVariantBinned) {
     BinArgs<KeyT, WT> b{a.keys, a.weights, a.n, a.coeffs, a.rows, a.log2m, plan.log2g, plan.log2r, plan.tiles,
                         plan.recs, plan.desc, a.table, a.flags};
-    static bool attr_set = false;  // dynamic LDS above 64 KiB needs the kernel attribute
-    if (!attr_set) {
-      set_accumulate_attribute();
-      (void)hipFuncSetAttribute((const void*)k_bin<PRIME, MODE, K, KeyT, WT, true>,
+    // dynamic LDS above 64 KiB needs the kernel attribute, once per device
+    static std::atomic<uint64_t> attr_done{0};
+    hipError_t ea = once_per_device(attr_done, [] {
+      hipError_t e = set_accumulate_attribute();
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_bin<PRIME, MODE, K, KeyT, WT, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      attr_set = true;
-    }
+      return e;
+    });
+    if (ea != hipSuccess) return ea;
     auto launch_bin = [&](bool dedup, uint32_t lds) {
       if (plan.wave_tiles && dedup)
         hipLaunchKernelGGL((k_bin_wave<PRIME, MODE, K, KeyT, WT, true>), dim3(plan.blocks), dim3(kBlock), lds, st, b);
@@ -1071,6 +1212,19 @@ hipError_t launch_update_t(const UpdatePlan& plan, const UpdateArgs<KeyT, WT>& a
     AccArgs c{plan.recs, plan.desc, plan.tiles, a.rows, a.log2m, plan.log2g, plan.log2r, plan.acc_slices,
               plan.wave_tiles ? kWaveTile : kBinTile, a.table};
     return launch_accumulate(c, plan.acc_blocks, plan.acc_lds_bytes, st);
+  }
+  if (plan.variant == kVariantRows) {
+    static std::atomic<uint64_t> attr_done{0};
+    hipError_t ea = once_per_device(attr_done, [] {
+      return hipFuncSetAttribute((const void*)k_update_rows<PRIME, MODE, K, KeyT, WT>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowLdsBytes);
+    });
+    if (ea != hipSuccess) return ea;
+    RowArgs<KeyT, WT> r{a.keys, a.weights, a.n, a.coeffs, a.rows, a.log2m, plan.rpg, a.rows / plan.rpg,
+                        plan.tiles, a.table, a.flags};
+    hipLaunchKernelGGL((k_update_rows<PRIME, MODE, K, KeyT, WT>), dim3(plan.blocks), dim3(kRowBlock), plan.lds_bytes,
+                       st, r);
+    return hipGetLastError();
   }
   if (plan.variant == kVariantLds) {
     hipLaunchKernelGGL((k_update_lds<PRIME, MODE, K, KeyT, WT>), dim3(plan.blocks), dim3(kBlock), plan.lds_bytes, st, a);

@@ -255,9 +255,9 @@ hipError_t launch_batch_acc(const BatchRound& rd, uint32_t lds_bytes, hipStream_
 
 // pass 2 holds up to 2^kMaxRangeLog2 int64 counters in dynamic LDS (above the
 // 64 KiB default)
-void set_accumulate_attribute() {
-  (void)hipFuncSetAttribute((const void*)k_accumulate, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(sizeof(unsigned long long) << kMaxRangeLog2));
+hipError_t set_accumulate_attribute() {
+  return hipFuncSetAttribute((const void*)k_accumulate, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(sizeof(unsigned long long) << kMaxRangeLog2));
 }
 
 hipError_t set_batch_acc_attribute() {

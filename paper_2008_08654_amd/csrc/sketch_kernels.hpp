@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "field.hpp"
 
 namespace mcs {
@@ -29,6 +31,14 @@ constexpr uint32_t kFlagOverflow = 2u;
 constexpr int kVariantLds = 0;
 constexpr int kVariantGlobal = 1;
 constexpr int kVariantBinned = 2;
+constexpr int kVariantRows = 3;
+
+// row-resident update (tables of up to 2^16 buckets per row)
+constexpr int kRowBlock = 1024;                     // 16 wave64s, one block per CU
+constexpr int kRowKpt = 8;                          // keys per thread per tile
+constexpr uint32_t kRowTile = kRowBlock * kRowKpt;  // keys per tile
+constexpr uint32_t kRowMaxLog2m = 16;               // a row of 16-bit fields fits LDS
+constexpr uint32_t kRowLdsBytes = 160 * 1024;       // LDS a block may hold
 
 // two-pass (binned) update
 constexpr int kBinKpt = 8;                          // keys per thread in a pass-1 tile
@@ -58,6 +68,26 @@ struct UpdatePlan {
   bool wave_tiles;      // pass 1 with one tile per wave (k_bin_wave)
   uint32_t* recs;       // [tiles][rows][kBinTile]
   uint32_t* desc;       // [tiles][rows][G + 1]
+  // row-resident variant
+  uint32_t rpg;         // rows per row group (a divisor of rows)
+};
+
+// Row-resident update: block b holds the 16-bit fields of row group b mod
+// groups (rpg rows of 2^log2m buckets) and takes the tiles rank, rank + cnt,
+// ... (rank = b / groups, cnt = blocks of its group).
+template <typename KeyT, typename WT>
+struct RowArgs {
+  const KeyT* keys;
+  const WT* weights;
+  uint64_t n;
+  const uint4* coeffs;
+  uint32_t rows;
+  uint32_t log2m;
+  uint32_t rpg;
+  uint32_t groups;
+  uint32_t tiles;
+  unsigned long long* table;
+  uint32_t* flags;
 };
 
 template <typename KeyT, typename WT>
@@ -236,6 +266,21 @@ struct BatchLaunch {
 };
 hipError_t launch_batch(const BatchLaunch& b, hipStream_t st);
 
+// Calls set() once per device (thread-safe; two threads may both call it, which
+// is harmless for idempotent attribute settings): a kernel attribute such as the
+// dynamic-LDS limit above 64 KiB must be in place before the first launch.
+template <typename F>
+inline hipError_t once_per_device(std::atomic<uint64_t>& done, F set) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const uint64_t bit = 1ull << (dev & 63);
+  if (done.load(std::memory_order_acquire) & bit) return hipSuccess;
+  e = set();
+  if (e == hipSuccess) done.fetch_or(bit, std::memory_order_acq_rel);
+  return e;
+}
+
 // Launchers per (prime, mode), one pair instantiated per translation unit;
 // launch_update / launch_query / launch_batch dispatch to them.
 template <int PRIME, int MODE>
@@ -247,7 +292,7 @@ hipError_t launch_query_pm(const QueryArgsAny& a, hipStream_t st);
 // pass-2 launches and LDS attributes shared by every instantiation
 hipError_t launch_accumulate(const AccArgs& c, uint32_t blocks, uint32_t lds_bytes, hipStream_t st);
 hipError_t launch_batch_acc(const BatchRound& rd, uint32_t lds_bytes, hipStream_t st);
-void set_accumulate_attribute();
+hipError_t set_accumulate_attribute();
 hipError_t set_batch_acc_attribute();
 
 // LDS bytes of one wave of the wave-tile pass 1:

@@ -63,3 +63,15 @@ def test_package_has_no_cpu_fallback():
     for path in glob.glob(os.path.join(pkg, "*.py")):
         src = open(path).read()
         assert "import oracle" not in src and "from oracle" not in src, path
+
+
+def test_hip_error_status_mapping(mcs):
+    """Out of memory is CS_ENOMEM; every other HIP error, such as the fault an earlier
+    kernel leaves behind (which later runtime calls, allocations included, keep
+    returning), is CS_EDEVICE rather than a misleading CS_ENOMEM."""
+    f = mcs.lib().cs_status_from_hip_error
+    assert f(0) == mcs.CS_OK
+    assert f(2) == mcs.CS_ENOMEM          # hipErrorOutOfMemory
+    assert f(1) == mcs.CS_EDEVICE         # hipErrorInvalidValue
+    assert f(700) == mcs.CS_EDEVICE       # hipErrorIllegalAddress
+    assert f(719) == mcs.CS_EDEVICE       # hipErrorLaunchFailure

@@ -110,6 +110,29 @@ def test_large_table_zipf_two_for_one_and_two_poly():
         _check_sketch(sk, keys, w)
 
 
+@pytest.mark.parametrize("mode", [0, 2])
+def test_full_size_zipf_beyond_one_round(mode):
+    """t = 9, m = 2^16 on 2^27 + 4099 Zipf(1.1) keys with int32 weights in [-100, 100]:
+    the workload's shape at half its key count, past the 2^27 keys of one two-pass round,
+    so the round loop and its ragged last round meet the oracle (the sketch is linear,
+    Section 1.3.1, so rounds add up to the same table).  The automatic path and the
+    forced two-pass path are both compared, counter by counter."""
+    n = (1 << 27) + 4099
+    keys, w = W.stream_zipf_u64(n, device=DEV)
+    torch.cuda.synchronize()
+    print(f"full-size parity: mode {mode}, n = {n}", flush=True)
+    auto = _make(9, 1 << 16, M.CS_P61, seed=1002, mode=mode)
+    auto.update(keys, w)
+    binned = _make(9, 1 << 16, M.CS_P61, seed=1002, mode=mode)
+    binned.set_update_path(M.CS_PATH_BINNED)
+    binned.update(keys, w)
+    want = _oracle_table(auto, keys, w)
+    _check_sketch(auto, keys, w, table=want)
+    _check_sketch(binned, keys, w, table=want)
+    auto.close()
+    binned.close()
+
+
 @pytest.mark.parametrize("path", [2, 3, 4])
 @pytest.mark.parametrize("rows,log2m,prime,mode", [
     (9, 16, 1, 0), (9, 16, 1, 2), (5, 20, 2, 0), (64, 10, 1, 1), (3, 15, 2, 2), (2, 22, 1, 0),
