@@ -202,6 +202,7 @@ def run_sketch(args, wl):
     sk = M.Sketch(rows, m, prime=prime, seed=wl["seed"], mode=mode)
     if args.path:
         sk.set_update_path(args.path)
+    sk.reserve(n)  # one workspace for the largest rounds (two-pass path only), outside the timed steps
     L = M.lib()
     stream = _stream_ptr(torch)
     kp, wp = ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(w.data_ptr())

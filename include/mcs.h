@@ -88,6 +88,16 @@ cs_status cs_create_with_coeffs(uint32_t rows, uint64_t buckets, cs_prime prime,
 /* Waits for the sketch's work and frees it.  NULL is accepted. */
 void cs_destroy(cs_sketch* s);
 
+/* Workspace.  The two-pass update path (BINNED) runs in rounds of at most
+ * 2^27 keys through a workspace the sketch owns: records and group offsets
+ * of the round, 4 * rows * (1 + about 1/16) bytes per key.  cs_create and
+ * cs_set_update_path reserve one for rounds of 2^20 keys when the sketch's
+ * path needs it; cs_reserve grows it to rounds of `keys` keys (fewer, larger
+ * rounds).  cs_update never allocates: it runs as many rounds as its n needs
+ * over the workspace it finds.  cs_reserve waits for the device before it
+ * replaces a workspace.  Paths without a workspace reserve nothing. */
+cs_status cs_reserve(cs_sketch* s, uint64_t keys);
+
 /* ---------------------------------------------------------------------------
  * cs_update -- Algorithm 2 "Process(x, D)" for a batch: for every i < n and
  * every row j, C[j][i_j(x_i)] += s_j(x_i) * D_i, with int64 two's-complement

@@ -85,6 +85,7 @@ def lib() -> ctypes.CDLL:
             "cs_server_get_stats": [P, P],
             "cs_server_replay": [P, P, u32, P, P],
             "cs_status_from_hip_error": [i32],
+            "cs_reserve": [P, u64],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -225,6 +226,10 @@ class Sketch:
 
     def set_update_path(self, path: int):
         _check(lib().cs_set_update_path(self._h, path))
+
+    def reserve(self, keys: int):
+        """Workspace for two-pass rounds of `keys` keys (see cs_reserve)."""
+        _check(lib().cs_reserve(self._h, keys))
 
     def reset(self, stream=None):
         _check(lib().cs_reset(self._h, _stream(stream)))

@@ -152,6 +152,8 @@ static cs_status check_shape(uint32_t rows, uint64_t buckets, cs_prime prime, cs
   return CS_OK;
 }
 
+static cs_status reserve_for(cs_sketch* s, uint64_t keys);
+
 static uint32_t est_slices_for(uint32_t log2m) {
   return (uint32_t)std::min<uint64_t>(256, std::max<uint64_t>(1, (1ull << log2m) / 16384));
 }
@@ -163,7 +165,7 @@ size_t mcs::sketch_device_bytes(uint32_t rows, uint32_t log2m, cs_mode mode, uin
 }
 
 static cs_status create_common(uint32_t rows, uint64_t buckets, cs_prime prime, cs_mode mode, uint32_t k,
-                               const std::vector<uint64_t>& coeffs, cs_sketch** out) {
+                               const std::vector<uint64_t>& coeffs, bool reserve, cs_sketch** out) {
   if (!out) return fail(CS_EINVAL, "out is NULL");
   *out = nullptr;
   int l;
@@ -212,6 +214,14 @@ static cs_status create_common(uint32_t rows, uint64_t buckets, cs_prime prime, 
     cs_destroy(s);
     return hip_fail(e, "sketch initialisation");
   }
+  // the automatic path's workspace, if it needs one, for rounds of the default size
+  if (reserve) {
+    cs_status rs = reserve_for(s, kDefaultRoundKeys);
+    if (rs != CS_OK) {
+      cs_destroy(s);
+      return rs;
+    }
+  }
   *out = s;
   return CS_OK;
 }
@@ -223,7 +233,17 @@ extern "C" cs_status cs_create_ex(uint32_t rows, uint64_t buckets, cs_prime prim
   if (st != CS_OK) return st;
   std::vector<uint64_t> c;
   expand_seed(prime, seed, (size_t)rows * npoly(mode) * k, c);
-  return create_common(rows, buckets, prime, mode, k, c, out);
+  return create_common(rows, buckets, prime, mode, k, c, true, out);
+}
+
+cs_status mcs::create_unreserved(uint32_t rows, uint64_t buckets, cs_prime prime, uint64_t seed, cs_mode mode,
+                                 uint32_t k, cs_sketch** out) {
+  int l;
+  cs_status st = check_shape(rows, buckets, prime, mode, k, &l);
+  if (st != CS_OK) return st;
+  std::vector<uint64_t> c;
+  expand_seed(prime, seed, (size_t)rows * npoly(mode) * k, c);
+  return create_common(rows, buckets, prime, mode, k, c, false, out);
 }
 
 extern "C" cs_status cs_create(uint32_t rows, uint64_t buckets, cs_prime prime, uint64_t seed, cs_sketch** out) {
@@ -250,7 +270,7 @@ extern "C" cs_status cs_create_with_coeffs(uint32_t rows, uint64_t buckets, cs_p
         return fail(CS_EINVAL, "coefficient %zu is not below p", i);
     }
   }
-  return create_common(rows, buckets, prime, mode, k, c, out);
+  return create_common(rows, buckets, prime, mode, k, c, true, out);
 }
 
 extern "C" void cs_destroy(cs_sketch* s) {
@@ -381,13 +401,25 @@ extern "C" cs_status cs_update(cs_sketch* s, const void* keys, cs_dtype key_type
   if (!keys || !weights) return fail(CS_EINVAL, "keys or weights is NULL");
   if (n > kMaxUpdateKeys) return fail(CS_EINVAL, "at most 2^40 keys per call");
   UpdatePlan plan = plan_update(s, n);
-  return enqueue_update(s, plan, keys, kb, weights, wb, n, stream);
+  return enqueue_update(s, plan, keys, kb, weights, wb, n, s->d_work, s->work_bytes, stream);
 }
 
-static cs_status ensure_workspace(cs_sketch* s, size_t bytes) {
+// Workspace of the two-pass update for rounds of `keys` keys (records,
+// descriptors and the combining probe's counts).
+static size_t twopass_work_bytes(const cs_sketch* s, const UpdatePlan& plan, uint64_t keys) {
+  const uint32_t G = 1u << plan.log2g;
+  const uint64_t tk = plan.wave_tiles ? kWaveTile : kBinTile;
+  const uint64_t tiles = (std::min<uint64_t>(keys, kBinChunkKeys) + tk - 1) / tk;
+  return (size_t)tiles * s->rows * (tk + G + 1) * 4 + 2 * kProbeTiles * sizeof(uint32_t);
+}
+
+// Grows the sketch's workspace to `bytes` (synchronising: the old one is freed).
+static cs_status grow_workspace(cs_sketch* s, size_t bytes) {
   if (s->work_bytes >= bytes) return CS_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "workspace growth");
   release_workspace(s);
-  hipError_t e = hipMalloc(&s->d_work, bytes);
+  e = hipMalloc(&s->d_work, bytes);
   if (e != hipSuccess) {
     s->d_work = nullptr;
     // out of memory is CS_ENOMEM; any other error (a fault an earlier kernel left
@@ -398,8 +430,26 @@ static cs_status ensure_workspace(cs_sketch* s, size_t bytes) {
   return CS_OK;
 }
 
+// Reserves the workspace that updates of `keys` keys take on the sketch's
+// current path (the two-pass path only; the others need none).
+static cs_status reserve_for(cs_sketch* s, uint64_t keys) {
+  const UpdatePlan plan = plan_update(s, std::max<uint64_t>(keys, 1));
+  if (plan.variant != kVariantBinned) return CS_OK;
+  return grow_workspace(s, twopass_work_bytes(s, plan, keys));
+}
+
+extern "C" cs_status cs_reserve(cs_sketch* s, uint64_t keys) {
+  if (!s) return fail(CS_EINVAL, "sketch is NULL");
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (cur != s->device) (void)hipSetDevice(s->device);
+  cs_status st = reserve_for(s, keys);
+  if (cur >= 0 && cur != s->device) (void)hipSetDevice(cur);
+  return st;
+}
+
 cs_status mcs::enqueue_update(cs_sketch* s, const UpdatePlan& plan, const void* keys, int kb, const void* weights,
-                              int wb, uint64_t n, hipStream_t stream) {
+                              int wb, uint64_t n, void* work, size_t work_bytes, hipStream_t stream) {
   UpdateArgsAny a{};
   a.prime = s->prime == CS_P61 ? kPrime61 : kPrime89;
   a.mode = (int)s->mode;
@@ -415,13 +465,17 @@ cs_status mcs::enqueue_update(cs_sketch* s, const UpdatePlan& plan, const void* 
     const DeviceInfo& dev = device_info(s->device);
     const uint32_t G = 1u << plan.log2g;
     const uint64_t tk = plan.wave_tiles ? kWaveTile : kBinTile;
-    const uint64_t chunk = std::min<uint64_t>(n, kBinChunkKeys);
+    // rounds as large as the workspace holds (at most kBinChunkKeys keys)
+    const size_t probe_bytes = 2 * kProbeTiles * sizeof(uint32_t);
+    const size_t per_tile = (size_t)s->rows * (tk + G + 1) * 4;
+    const uint64_t fit_tiles = work_bytes > probe_bytes ? (work_bytes - probe_bytes) / per_tile : 0;
+    if (fit_tiles == 0 || !work)
+      return fail(CS_EINVAL, "the two-pass update needs a workspace of at least %zu bytes (cs_reserve)",
+                  per_tile + probe_bytes);
+    const uint64_t chunk = std::min<uint64_t>(std::min<uint64_t>(n, kBinChunkKeys), fit_tiles * tk);
     const uint64_t tiles_c = (chunk + tk - 1) / tk;
     const size_t rec_bytes = (size_t)tiles_c * s->rows * tk * 4;
     const size_t desc_bytes = (size_t)tiles_c * s->rows * (G + 1) * 4;
-    const size_t probe_bytes = plan.combine_auto ? 2 * kProbeTiles * sizeof(uint32_t) : 0;
-    cs_status st = ensure_workspace(s, rec_bytes + desc_bytes + probe_bytes);
-    if (st != CS_OK) return st;
     for (uint64_t off = 0; off < n; off += chunk) {
       const uint64_t len = std::min<uint64_t>(chunk, n - off);
       UpdatePlan p = plan;
@@ -433,9 +487,9 @@ cs_status mcs::enqueue_update(cs_sketch* s, const UpdatePlan& plan, const void* 
       uint64_t slices = (4ull * plan.acc_blocks + parts - 1) / parts;
       slices = std::max<uint64_t>(1, std::min<uint64_t>(slices, std::max<uint64_t>(1, p.tiles / 64)));
       p.acc_slices = (uint32_t)slices;
-      p.recs = (uint32_t*)s->d_work;
-      p.desc = (uint32_t*)((char*)s->d_work + rec_bytes);
-      p.probe = plan.combine_auto ? (uint32_t*)((char*)s->d_work + rec_bytes + desc_bytes) : nullptr;
+      p.recs = (uint32_t*)work;
+      p.desc = (uint32_t*)((char*)work + rec_bytes);
+      p.probe = plan.combine_auto ? (uint32_t*)((char*)work + rec_bytes + desc_bytes) : nullptr;
       a.keys = (const char*)keys + off * kb;
       a.weights = (const char*)weights + off * wb;
       a.n = len;
@@ -467,7 +521,8 @@ extern "C" cs_status cs_set_update_path(cs_sketch* s, int path) {
   if (path < CS_PATH_AUTO || path > CS_PATH_ROWS) return fail(CS_EINVAL, "unknown update path %d", path);
   s->path = path == CS_PATH_BINNED_NOCOMBINE ? CS_PATH_BINNED : path;
   s->combine = path != CS_PATH_BINNED_NOCOMBINE;
-  return CS_OK;
+  // a path with a workspace gets the default one now, so that cs_update never allocates
+  return s->work_bytes ? CS_OK : reserve_for(s, kDefaultRoundKeys);
 }
 
 // ---------------------------------------------------------------------------

@@ -25,7 +25,7 @@ struct cs_sketch {
   int64_t* d_est_out = nullptr;    // median, rows values, flags
   int64_t* h_est_out = nullptr;    // pinned copy of d_est_out
   uint32_t est_slices = 1;
-  void* d_work = nullptr;          // workspace of the two-pass update (bins)
+  void* d_work = nullptr;          // workspace of the two-pass update (cs_reserve)
   size_t work_bytes = 0;
   int path = 0;                    // 0 auto, else forced cs_update path (CS_PATH_*)
   bool combine = true;             // two-pass update combines repeated keys of a tile
@@ -37,6 +37,7 @@ constexpr uint64_t kLdsTableMax = 64 * 1024;   // tables up to this size use the
 constexpr uint64_t kLdsPerCu = 160 * 1024;
 constexpr uint64_t kBinChunkKeys = 1ull << 27;  // keys per pass-1/pass-2 round of the binned update
 constexpr uint64_t kMaxUpdateKeys = 1ull << 40;  // keys per cs_update call (tile counts fit 32 bits)
+constexpr uint64_t kDefaultRoundKeys = 1ull << 20;  // two-pass round a new sketch reserves a workspace for
 
 struct DeviceInfo {
   bool valid = false;
@@ -52,8 +53,14 @@ cs_status status_of(hipError_t e);
 cs_status hip_fail(hipError_t e, const char* what);
 
 UpdatePlan plan_update(const cs_sketch* s, uint64_t n);
+// Enqueues the plan's launches; the two-pass path runs in rounds as large as
+// `work` (work_bytes) holds.  Allocates nothing.
 cs_status enqueue_update(cs_sketch* s, const UpdatePlan& plan, const void* keys, int kb, const void* weights, int wb,
-                         uint64_t n, hipStream_t stream);
+                         uint64_t n, void* work, size_t work_bytes, hipStream_t stream);
+// cs_create_ex without the default workspace (for sketches that cs_update
+// never touches, such as the serving runtime's tenants).
+cs_status create_unreserved(uint32_t rows, uint64_t buckets, cs_prime prime, uint64_t seed, cs_mode mode, uint32_t k,
+                            cs_sketch** out);
 // Status for device-reported flags (kFlagDomain takes precedence); sets the
 // last-error message.
 cs_status flags_status(uint32_t flags);

@@ -474,7 +474,7 @@ extern "C" cs_status cs_server_admit(cs_server* S, uint32_t rows, uint64_t bucke
   cs_status st;
   {
     DeviceGuard g(S->device);
-    st = cs_create_ex(rows, buckets, S->cprime, seed, S->cmode, S->k, &sk);
+    st = create_unreserved(rows, buckets, S->cprime, seed, S->cmode, S->k, &sk);
   }
   std::lock_guard<std::mutex> lk(S->mu);
   if (st != CS_OK) {

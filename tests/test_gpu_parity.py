@@ -133,7 +133,7 @@ def test_full_size_zipf_beyond_one_round(mode):
     binned.close()
 
 
-@pytest.mark.parametrize("path", [2, 3, 4])
+@pytest.mark.parametrize("path", [2, 3, 4, 5])
 @pytest.mark.parametrize("rows,log2m,prime,mode", [
     (9, 16, 1, 0), (9, 16, 1, 2), (5, 20, 2, 0), (64, 10, 1, 1), (3, 15, 2, 2), (2, 22, 1, 0),
     # one or two bucket ranges per row, where rows * ranges * 4 bytes of
@@ -164,6 +164,65 @@ def test_forced_paths_match_oracle(path, rows, log2m, prime, mode):
                               O.coeffs_from_seed(PRIMES[prime], rows, mode, seed=500 + log2m),
                               _u64(keys[: n // 3]), w[: n // 3].cpu().numpy(), table=want)
     _check_sketch(sk, keys, w, table=want)
+
+
+@pytest.mark.parametrize("rows,buckets,prime,mode,k,kt,wt", [
+    (9, 1 << 16, 1, 0, 4, "u64", "i32"),    # the workload's shape: one row per block
+    (9, 1 << 16, 1, 2, 4, "u64", "i32"),    # two polynomials
+    (9, 1 << 12, 1, 0, 4, "u32", "i64"),    # all nine rows in one block
+    (6, 1 << 15, 2, 1, 4, "u64", "i64"),    # two rows per block, 2^89 - 1, Algorithm 3's bit layout
+    (8, 1 << 14, 1, 0, 8, "u64", "i32"),    # four rows per block, k = 8
+    (7, 12345, 1, 3, 2, "u64", "i32"),      # any bucket count, odd r (the padding bucket shares r - 1's word)
+    (3, 65535, 2, 3, 4, "u32", "i32"),      # any bucket count, 2^16 - 1 buckets
+    (1, 1 << 16, 1, 0, 4, "u64", "i64"),    # one row
+    (5, 2, 1, 0, 4, "u64", "i32"),          # two buckets: one word per row
+])
+def test_rows_path_matches_oracle(rows, buckets, prime, mode, k, kt, wt):
+    """The row-resident update (16-bit fields in LDS, wraps carried into the int64
+    counters) gives the oracle's counters: ragged tiles, keys past 2^32 (the two-limb
+    hash), and weights at the edge of the fields (+-(2^15 - 1) stay in LDS, +-2^15 and
+    beyond go to the counters directly)."""
+    n = 3 * 8192 + 1234
+    seed = 800 + rows + (buckets & 0xFFFF)
+    keys = W.zipf(seed, n, 1.1, 1 << 32)
+    if kt == "u64":
+        keys[::5] |= W.uniform_u64(seed, keys[::5].numel()) & (((1 << 60) - 1) ^ 0xFFFFFFFF)
+    w = W.bounded_int(seed, n, -100, 100)
+    w[1::61] = (1 << 15) - 1
+    w[2::61] = -(1 << 15) + 1
+    w[3::61] = 1 << 15
+    w[4::61] = -(1 << 15)
+    w[5::61] = (1 << 31) - 1 if wt == "i32" else (1 << 62) + 3
+    w[6::61] = -(1 << 31) if wt == "i32" else -(1 << 62) - 5
+    keys = keys.to(torch.int32) if kt == "u32" else keys
+    w = w.to(torch.int32) if wt == "i32" else w
+    keys, w = keys.to(DEV), w.to(DEV)
+    sk = _make(rows, buckets, prime, seed=seed, mode=mode, k=k)
+    sk.set_update_path(M.CS_PATH_ROWS)
+    sk.update(keys, w)
+    sk.update(keys[: n // 3].contiguous(), w[: n // 3].contiguous())
+    want = _oracle_table(sk, keys, w)
+    O.cs_update(PRIMES[prime], mode, rows, buckets, O.coeffs_from_seed(PRIMES[prime], rows, mode, seed=seed, k=k),
+                _u64(keys[: n // 3]), w[: n // 3].cpu().numpy().astype(np.int64), table=want, k=k)
+    _check_sketch(sk, keys, w, table=want)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_rows_path_field_wraps(mode):
+    """Few keys with weights +-(2^15 - 1): every field drifts past its 16-bit range many
+    times in both directions (low and high halves, carries out of the word), and each
+    wrap must reach the int64 counters exactly."""
+    n = 1 << 20
+    keys = (W.uniform_u64(11, n) & 63) * 0x9E3779B97F4A7C15 & ((1 << 60) - 1)
+    w = torch.full((n,), (1 << 15) - 1, dtype=torch.int64)
+    w[(n * 3) // 5:] = -(1 << 15) + 1
+    w[::3] = W.bounded_int(12, w[::3].numel(), -(1 << 15) + 1, (1 << 15) - 1)
+    keys, w = keys.to(DEV), w.to(torch.int32).to(DEV)
+    sk = _make(9, 1 << 16, M.CS_P61, seed=1002, mode=mode)
+    sk.set_update_path(M.CS_PATH_ROWS)
+    sk.update(keys, w)
+    table = _check_sketch(sk, keys, w)
+    assert int(np.abs(table).max()) > 1 << 20  # the counters went far beyond 16 bits
 
 
 @pytest.mark.parametrize("path", [3, 4])
