@@ -114,12 +114,15 @@ def measured_traffic(workload: str, n: int):
     return entry.get("hbm_bytes_per_launch")
 
 
-def update_kernels(sk, n) -> str:
-    """The dispatches one cs_update of n keys makes (to match against a kernel profile)."""
+def update_kernels(sk, n, path=0) -> str:
+    """The dispatches one cs_update of n keys makes on the automatic (or forced) path."""
     chunks = -(-n // (1 << 27))
-    if sk.rows * sk.buckets * 8 <= 65536:
+    pitch = 1 << (sk.buckets - 1).bit_length()
+    if path in (0, 1) and sk.rows * pitch * 8 <= 65536:
         return "1 x k_update_lds"
-    return f"{chunks} x (k_bin_wave or k_bin) + {chunks} x k_accumulate (chunks of 2^27 keys)"
+    if path in (0, 5) and pitch <= 1 << 16:
+        return "1 x k_update_rows"
+    return f"{chunks} x (k_bin_wave or k_bin) + {chunks} x k_accumulate (rounds of 2^27 keys)"
 
 
 def _stream_ptr(torch):
@@ -250,7 +253,7 @@ def run_sketch(args, wl):
                         "traffic": measured_traffic(args.workload, n),
                         "algorithmic_bytes_per_launch": bytes_key * n,
                         "kernel": "cs_update", "kernel_avg_ms": round(upd_avg_ms, 4),
-                        "kernels_per_launch": update_kernels(sk, n),
+                        "kernels_per_launch": update_kernels(sk, n, args.path),
                         "algorithmic_ops_per_key": ops_key,
                         "hbm_frac_of_input_stream": round(bytes_key * n / (upd_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
     if not args.no_cpu_baseline:
@@ -648,6 +651,64 @@ def run_divmod_bsweep(args):
     return out
 
 
+CEILING_PROBES = [  # (probe id, name, unit of one operation, iters, buffer bytes)
+    (0, "v_add_u32", "lane-instructions", 2000, 8),
+    (1, "v_mad_u64_u32", "lane-instructions", 2000, 8),
+    (2, "v_lshl_add_u64", "lane-instructions", 2000, 8),
+    (3, "v_lshrrev_b64", "lane-instructions", 2000, 8),
+    (4, "HBM read stream (16-byte loads, 4 GiB)", "bytes", 0, 1 << 32),
+    (5, "ds_add_u64, random addresses of 64 KiB", "atomics", 1000, 8),
+    (6, "ds_add_rtn_u32, random addresses of 64 KiB", "atomics", 1000, 8),
+    (7, "global int64 atomics, random over 40 KiB", "atomics", 64, 40 << 10),
+    (7, "global int64 atomics, random over 4.5 MiB", "atomics", 64, 9 << 19),
+    (7, "global int64 atomics, random over 40 MiB", "atomics", 64, 40 << 20),
+    (8, "global int64 atomics, coalesced over 4.5 MiB", "atomics", 512, 9 << 19),
+]
+
+
+def run_ceilings(args):
+    """Measured ceilings: issue rates of the VALU instructions of the Horner step (in
+    lane-instructions per second against the 256 CU x 4 SIMD x 16 lanes x 2.4 GHz peak),
+    the HBM read stream, LDS atomics and device-scope global atomics."""
+    import torch
+    import paper_2008_08654_amd as M
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    L = M.lib()
+    stream = _stream_ptr(torch)
+    results = []
+    for probe, name, unit, iters, nbytes in CEILING_PROBES:
+        buf = torch.zeros(max(nbytes, 8) // 8, dtype=torch.int64, device=dev)
+        ops = ctypes.c_uint64()
+        times = []
+        for rep in range(args.warmup + max(args.steps, 5)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            M._check(L.cs_ceiling_run(probe, ctypes.c_void_p(buf.data_ptr()), buf.numel() * 8, iters,
+                                      ctypes.byref(ops), stream))
+            b.record()
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                times.append(a.elapsed_time(b))
+        times.sort()
+        ms = times[len(times) // 2]
+        rate = ops.value / (ms * 1e-3)
+        rec = {"probe": name, "unit": unit, "ops_per_launch": ops.value, "median_ms": round(ms, 4),
+               "rate": rate}
+        if unit == "lane-instructions":
+            rec["frac_of_full_rate"] = round(rate / (VALU_PEAK_TOPS * 1e12), 3)
+        _log(f"ceilings: {name}: {rate:.4g} {unit}/s in {ms:.3f} ms")
+        results.append(rec)
+        del buf
+    mad = next(r for r in results if r["probe"] == "v_mad_u64_u32")
+    return {"metric": "measured ceilings (VALU issue rates, HBM read, LDS and global atomics)",
+            "value": round(mad["rate"] / 1e12, 3), "unit": "T lane-instructions/s (v_mad_u64_u32)", "n_gpus": 1,
+            "steps": max(args.steps, 5), "warmup": args.warmup, "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": "ceilings", "valu_peak_tops": round(VALU_PEAK_TOPS, 2),
+                       "probes": results}}
+
+
 def run_divmod(args, wl):
     import numpy as np
     import torch
@@ -714,7 +775,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="single_stream_zipf",
                     choices=sorted(SKETCH_WORKLOADS) + sorted(DIVMOD_WORKLOADS) + sorted(MAP_WORKLOADS)
-                    + ["batched", "served", "divmod_bsweep"])
+                    + ["batched", "served", "divmod_bsweep", "ceilings"])
     ap.add_argument("--n", type=int, default=None, help="override the number of keys / values")
     ap.add_argument("--path", type=int, default=0, help="force an update path (1 LDS, 2 global, 3 binned)")
     ap.add_argument("--direct-fraction", type=float, default=0.0,
@@ -736,7 +797,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.workload == "batched":
+    if args.workload == "ceilings":
+        out = run_ceilings(args)
+    elif args.workload == "batched":
         out = run_batched(args)
     elif args.workload == "served":
         out = run_served(args)

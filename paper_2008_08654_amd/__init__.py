@@ -86,6 +86,7 @@ def lib() -> ctypes.CDLL:
             "cs_server_replay": [P, P, u32, P, P],
             "cs_status_from_hip_error": [i32],
             "cs_reserve": [P, u64],
+            "cs_ceiling_run": [i32, P, u64, u32, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)

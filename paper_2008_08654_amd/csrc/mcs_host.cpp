@@ -338,6 +338,7 @@ UpdatePlan mcs::plan_update(const cs_sketch* s, uint64_t n) {
   int path = s->path;
   if (path == 0)
     path = cells * 8 <= kLdsTableMax ? CS_PATH_LDS
+           : rpg                     ? CS_PATH_ROWS
            : binned_fits(s, &log2g, &log2r) ? CS_PATH_BINNED
                                             : CS_PATH_GLOBAL;
   if (path == CS_PATH_LDS && cells * 8 > kLdsTableMax) path = CS_PATH_GLOBAL;

@@ -228,6 +228,36 @@ __device__ __forceinline__ void load_tile(const KeyT* __restrict__ keys, const W
   }
 }
 
+// Keys and weights at kp[j * 64], wp[j * 64], j < kKpt (all in range): one
+// base address per array and immediate offsets; every load is issued before
+// any value is used (as in load_tile).  big: some weight is outside
+// (-2^15, 2^15); any_hi: the or of the keys' high words.
+template <int kKpt, typename KeyT, typename WT>
+__device__ __forceinline__ void load_tile_full(const KeyT* __restrict__ kp, const WT* __restrict__ wp,
+                                               uint32_t (&x0)[kKpt], uint32_t (&x1)[kKpt], int32_t (&wf)[kKpt],
+                                               bool& big, uint32_t& any_hi) {
+  KeyT kr[kKpt];
+  WT wr[kKpt];
+#pragma unroll
+  for (int j = 0; j < kKpt; ++j) {
+    kr[j] = kp[j * 64];
+    wr[j] = wp[j * 64];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int j = 0; j < kKpt; ++j) {
+    const uint64_t k = (uint64_t)kr[j];
+    x0[j] = (uint32_t)k;
+    x1[j] = (uint32_t)(k >> 32);
+    any_hi |= x1[j];
+    if constexpr (sizeof(WT) == 4)
+      big |= (uint32_t)((int32_t)wr[j] + 32767) > 65534u;
+    else
+      big |= (uint64_t)((int64_t)wr[j] + 32767) > 65534u;
+    wf[j] = (int32_t)wr[j];
+  }
+}
+
 __device__ __forceinline__ unsigned long long signed_weight(int64_t w, uint32_t a) {
   return (unsigned long long)(a ? -w : w);
 }
@@ -376,17 +406,23 @@ __global__ __launch_bounds__(kBlock) void k_update_global(UpdateArgs<KeyT, WT> a
 // order.  Weights with |w| >= 2^15 skip the fields and go to the global
 // counters directly.
 // ---------------------------------------------------------------------------
-template <int PRIME, int MODE, int K, int NP, bool WIDE, typename KeyT, typename WT>
+// The rows of a row group for one wave's keys: hash, add each s*w into its
+// field, carry wraps into the global counters.  ESC: some keys have weights
+// that bypass the fields (esc[j]); without ESC every wf[j] is the key's weight.
+template <int PRIME, int MODE, int K, int NP, bool WIDE, bool ESC, typename KeyT, typename WT>
 __device__ __forceinline__ void rows_tile(const RowArgs<KeyT, WT>& args, uint32_t r0, uint32_t* words,
                                           const uint32_t (&x0)[kRowKpt], const uint32_t (&x1)[kRowKpt],
-                                          const int32_t (&wf)[kRowKpt], const int64_t (&wv)[kRowKpt],
-                                          const bool (&esc)[kRowKpt], bool any_esc) {
+                                          const int32_t (&wf)[kRowKpt], const int64_t* wv, const bool* esc,
+                                          bool any_esc) {
   const uint32_t m = 1u << args.log2m;
   const uint32_t amask = 2u * m - 4u;  // byte offset of a bucket's word in its row: code & amask
   for (uint32_t r = 0; r < args.rpg; ++r) {
     const uint32_t row = r0 + r;
     const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)row * NP * K);
-    unsigned char* const rowb = (unsigned char*)words + (size_t)r * 2u * m;
+    // byte offset of the row in LDS, a multiple of 2m, or-ed onto code & amask;
+    // kept in a vector register so that the and-or takes one instruction
+    uint32_t rowoff;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(rowoff) : "s"(r * 2u * m));
     uint32_t code[kRowKpt], old[kRowKpt], sh[kRowKpt];
     int32_t sw[kRowKpt];
 #pragma unroll
@@ -398,7 +434,7 @@ __device__ __forceinline__ void rows_tile(const RowArgs<KeyT, WT>& args, uint32_
       const int32_t sgn = __builtin_amdgcn_sbfe((int)code[j], 0, 1);
       sw[j] = (wf[j] ^ sgn) - sgn;
       sh[j] = (code[j] & 2u) << 3;
-      old[j] = atomicAdd((uint32_t*)(rowb + (code[j] & amask)), (uint32_t)sw[j] << sh[j]);
+      old[j] = atomicAdd((uint32_t*)((unsigned char*)words + ((code[j] & amask) | rowoff)), (uint32_t)sw[j] << sh[j]);
     }
     bool wr[kRowKpt];
     bool any_wr = false;
@@ -423,7 +459,7 @@ __device__ __forceinline__ void rows_tile(const RowArgs<KeyT, WT>& args, uint32_
           }
         }
     }
-    if (any_esc) {
+    if (ESC && any_esc) {
 #pragma unroll
       for (int j = 0; j < kRowKpt; ++j)
         if (esc[j]) {
@@ -436,7 +472,8 @@ __device__ __forceinline__ void rows_tile(const RowArgs<KeyT, WT>& args, uint32_
 
 template <int PRIME, int MODE, int K, typename KeyT, typename WT>
 __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> args) {
-  extern __shared__ __align__(16) uint32_t words[];
+  // static, so that LDS addresses need no base: one block per CU holds it all
+  __shared__ __align__(16) uint32_t words[kRowLdsBytes / 4];
   constexpr int NP = MODE == kTwoPoly ? 2 : 1;
   const uint32_t G = args.groups;
   const uint32_t g = blockIdx.x % G, rank = blockIdx.x / G;
@@ -451,13 +488,32 @@ __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> arg
     // wave `wave` takes keys [base, base + 64 * kRowKpt) of the tile
     const uint64_t base = (uint64_t)t * kRowTile + (uint64_t)wave * (64 * kRowKpt);
     if (base >= args.n) continue;
+    if (base + 64 * kRowKpt <= args.n) {  // a full wave tile (wave-uniform)
+      uint32_t x0[kRowKpt], x1[kRowKpt];
+      int32_t wf[kRowKpt];
+      bool big = false;
+      uint32_t any_hi = 0;
+      load_tile_full<kRowKpt>(args.keys + base + lane, args.weights + base + lane, x0, x1, wf, big, any_hi);
+      if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;  // key >= 2^60 breaks p >= 2u - 1
+      if (!__any(big)) {  // every weight fits a field: no per-key selects
+        const int64_t* nowv = nullptr;
+        const bool* noesc = nullptr;
+        if (PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0)) {
+          rows_tile<PRIME, MODE, K, NP, true, false>(args, r0, words, x0, x1, wf, nowv, noesc, false);
+        } else {
+          rows_tile<PRIME, MODE, K, NP, false, false>(args, r0, words, x0, x1, wf, nowv, noesc, false);
+        }
+        continue;
+      }
+      // rare: a weight beyond the fields; the tile is loaded again below
+    }
     uint32_t x0[kRowKpt], x1[kRowKpt];
     int64_t wv[kRowKpt];
     bool ok[kRowKpt];
-    load_tile<kRowKpt>(args.keys, args.weights, base, 64, lane, args.n, x0, x1, wv, ok);
-    uint32_t any_hi = 0;
     int32_t wf[kRowKpt];
     bool esc[kRowKpt];
+    load_tile<kRowKpt>(args.keys, args.weights, base, 64, lane, args.n, x0, x1, wv, ok);
+    uint32_t any_hi = 0;
     bool any_e = false;
 #pragma unroll
     for (int j = 0; j < kRowKpt; ++j) {
@@ -467,12 +523,12 @@ __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> arg
       esc[j] = ok[j] && !fits;
       any_e |= esc[j];
     }
-    if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;  // key >= 2^60 breaks p >= 2u - 1
+    if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;
     const bool any_esc = __any(any_e);
     if (PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0))
-      rows_tile<PRIME, MODE, K, NP, true>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
+      rows_tile<PRIME, MODE, K, NP, true, true>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
     else
-      rows_tile<PRIME, MODE, K, NP, false>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
+      rows_tile<PRIME, MODE, K, NP, false, true>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
   }
   if (bad) atomicOr(args.flags, kFlagDomain);
   __syncthreads();
@@ -1214,16 +1270,9 @@ hipError_t launch_update_t(const UpdatePlan& plan, const UpdateArgs<KeyT, WT>& a
     return launch_accumulate(c, plan.acc_blocks, plan.acc_lds_bytes, st);
   }
   if (plan.variant == kVariantRows) {
-    static std::atomic<uint64_t> attr_done{0};
-    hipError_t ea = once_per_device(attr_done, [] {
-      return hipFuncSetAttribute((const void*)k_update_rows<PRIME, MODE, K, KeyT, WT>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kRowLdsBytes);
-    });
-    if (ea != hipSuccess) return ea;
     RowArgs<KeyT, WT> r{a.keys, a.weights, a.n, a.coeffs, a.rows, a.log2m, plan.rpg, a.rows / plan.rpg,
                         plan.tiles, a.table, a.flags};
-    hipLaunchKernelGGL((k_update_rows<PRIME, MODE, K, KeyT, WT>), dim3(plan.blocks), dim3(kRowBlock), plan.lds_bytes,
-                       st, r);
+    hipLaunchKernelGGL((k_update_rows<PRIME, MODE, K, KeyT, WT>), dim3(plan.blocks), dim3(kRowBlock), 0, st, r);
     return hipGetLastError();
   }
   if (plan.variant == kVariantLds) {
