@@ -87,6 +87,7 @@ def lib() -> ctypes.CDLL:
             "cs_status_from_hip_error": [i32],
             "cs_reserve": [P, u64],
             "cs_ceiling_run": [i32, P, u64, u32, P, P],
+            "cs_update_noalloc": [P, P, i32, P, i32, u64, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -191,6 +192,14 @@ class Sketch:
             raise ValueError("keys/weights shorter than n")
         _check(lib().cs_update(self._h, _dev_ptr(keys), _key_dtype(keys), _dev_ptr(weights), _weight_dtype(weights),
                                n, _stream(stream)))
+
+    def update_noalloc(self, keys, weights, stream=None, n: int | None = None):
+        """cs_update_noalloc: the same update, no allocation (include/mcs_noalloc.h)."""
+        n = keys.numel() if n is None else n
+        if weights.numel() < n or keys.numel() < n:
+            raise ValueError("keys/weights shorter than n")
+        _check(lib().cs_update_noalloc(self._h, _dev_ptr(keys), _key_dtype(keys), _dev_ptr(weights),
+                                       _weight_dtype(weights), n, _stream(stream)))
 
     # Algorithm 2, Output + median over rows
     def estimate_f2(self, stream=None) -> tuple[int, np.ndarray]:
