@@ -33,21 +33,26 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.32 T 32-bit lane-ops/s (full-rate VALU)
+# ALU peak, from the unit counts: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.64 T lane-slots/s
+# (the fp32 vector peak of 157.3 TFLOP/s is this many fused multiply-adds).  A 32-bit
+# integer VALU instruction takes one slot per lane; the 64-bit ones of the hash
+# (v_mad_u64_u32, v_lshl_add_u64, v_lshrrev_b64) take two: measured by
+# `bench.py --workload ceilings` (profiles/ceilings.md) at 36.8-37.6 T lane-instructions/s
+# against 69.5 T for v_add_u32.
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12  # 78.64 T lane-slots/s
 HBM_PEAK_GBS = 8000.0
 METRIC = "Gkeys/s into Count Sketch (p=2^61-1, 4-universal) + % of binding roofline"
 
-# Algorithmic 32-bit VALU operations per key and row: the VALU instructions
-# (register moves not counted, so a lower bound) of the compiled straight-line
-# hash + final reduction + split of one row on gfx950, plus 2 per row for the
-# signed-weight select and the counter address / record.  Counts taken from the
-# gfx950 assembly of bucket_sign (profiles/valu_ops_per_key_row.md):
-#   p61, key < 2^32, two-for-one: 3 Horner steps x 6 + final reduction 4 + split = 22, + 2 = 24
-#   p61 two polynomials: 41 + 2 = 43
-#   p61 any bucket count (Algorithm 8): 25 + 2 = 27
-#   p89, 64-bit keys, two-for-one: 60 + 2 = 62
-OPS_PER_KEY_ROW = {("p61", 0): 24, ("p61", 2): 43, ("p89", 0): 62, ("p61", 3): 27}
-OPS_PER_KEY = 3  # weight negation (2) and domain check (1)
+# Algorithmic VALU slots per key and row: the VALU instructions (register moves not
+# counted, so a lower bound) of the compiled straight-line hash + final reduction +
+# split of one row on gfx950, 64-bit instructions weighted 2, plus 2 per row for the
+# signed weight and the counter address (profiles/valu_ops_per_key_row.md):
+#   p61, key < 2^32, two-for-one: 16 64-bit + 6 32-bit = 38, + 2 = 40
+#   p61 two polynomials: 32 64-bit + 9 32-bit = 73, + 2 = 75
+#   p61 any bucket count (Algorithm 8): 18 64-bit + 7 32-bit = 43, + 2 = 45
+#   p89, 64-bit keys, two-for-one: 41 64-bit + 19 32-bit = 101, + 2 = 103
+OPS_PER_KEY_ROW = {("p61", 0): 40, ("p61", 2): 75, ("p89", 0): 103, ("p61", 3): 45}
+OPS_PER_KEY = 3  # weight negation (2) and domain check (1), 32-bit
 
 SKETCH_WORKLOADS = {
     "single_stream_zipf": dict(n=1 << 28, rows=9, log2m=16, mode=0, prime="p61", keys="zipf", kbytes=8, wbytes=4,
@@ -249,7 +254,7 @@ def run_sketch(args, wl):
                       "update_only_gkeys_per_s": round(n / (upd_avg_ms * 1e-3) / 1e9, 3),
                       "input_generation_s": round(t_gen, 2)},
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                        "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                        "unit": "T VALU lane-slots/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                         "traffic": measured_traffic(args.workload, n),
                         "algorithmic_bytes_per_launch": bytes_key * n,
                         "kernel": "cs_update", "kernel_avg_ms": round(upd_avg_ms, 4),
@@ -361,7 +366,7 @@ def run_batched(args):
                       "batched_vs_plain_speedup": round(plain_wall_ms / (elapsed * 1e3 / args.steps), 2),
                       "input_generation_s": round(t_gen, 2)},
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                        "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                        "unit": "T VALU lane-slots/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
                         "kernel": "batched update (all launches)", "kernel_avg_ms": round(batch_ms, 4),
                         "algorithmic_ops_per_key": ops_key}}
     if not args.no_cpu_baseline:
@@ -475,7 +480,7 @@ def run_served(args):
                       "saturated_latency_p50_ms": lat_stats(res)["p50_ms"], "loads": loads,
                       "steps_run": stats.steps, "resident_bytes": stats.resident_bytes, "failed_requests": bad},
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                        "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                        "unit": "T VALU lane-slots/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
                         "kernel": "served steps (all launches, closed loop)", "algorithmic_ops_per_key": ops_key}}
     if not args.no_cpu_baseline:
         import oracle as O

@@ -160,7 +160,7 @@ static uint32_t est_slices_for(uint32_t log2m) {
 
 size_t mcs::sketch_device_bytes(uint32_t rows, uint32_t log2m, cs_mode mode, uint32_t k) {
   const size_t ncoef = (size_t)rows * npoly(mode) * k;
-  return ((size_t)rows << log2m) * 8 + ncoef * sizeof(uint4) + 64 +
+  return ((size_t)rows << log2m) * 8 + ncoef * sizeof(uint4) + 64 + sizeof(uint32_t) * kRowXcds * kMaxRows +
          sizeof(EstPartial) * rows * est_slices_for(log2m) + sizeof(int64_t) * (rows + 2);
 }
 
@@ -196,7 +196,8 @@ static cs_status create_common(uint32_t rows, uint64_t buckets, cs_prime prime, 
   hipError_t e;
   if ((e = hipMalloc(&s->d_table, cells * 8)) != hipSuccess ||
       (e = hipMalloc(&s->d_coeffs, ncoef * sizeof(uint4))) != hipSuccess ||
-      (e = hipMalloc(&s->d_flags, 64)) != hipSuccess) {
+      (e = hipMalloc(&s->d_flags, 64)) != hipSuccess ||
+      (e = hipMalloc(&s->d_queues, sizeof(uint32_t) * kRowXcds * kMaxRows)) != hipSuccess) {
     cs_destroy(s);
     return fail(CS_ENOMEM, "device allocation of %zu counters: %s", cells, hipGetErrorString(e));
   }
@@ -282,6 +283,7 @@ extern "C" void cs_destroy(cs_sketch* s) {
   if (s->d_table) (void)hipFree(s->d_table);
   if (s->d_coeffs) (void)hipFree(s->d_coeffs);
   if (s->d_flags) (void)hipFree(s->d_flags);
+  if (s->d_queues) (void)hipFree(s->d_queues);
   if (s->d_est_part) (void)hipFree(s->d_est_part);
   if (s->d_est_out) (void)hipFree(s->d_est_out);
   if (s->h_est_out) (void)hipHostFree(s->h_est_out);
@@ -352,6 +354,7 @@ UpdatePlan mcs::plan_update(const cs_sketch* s, uint64_t n) {
     const uint64_t rtiles = (n + kRowTile - 1) / kRowTile;
     p.tiles = (uint32_t)std::min<uint64_t>(rtiles, 0xffffffffull);
     p.blocks = (uint32_t)std::max<uint64_t>(groups, std::min<uint64_t>((uint64_t)dev.cus, groups * rtiles));
+    p.queues = s->d_queues;
   } else if (path == CS_PATH_LDS) {
     p.variant = kVariantLds;
     p.lds_bytes = (uint32_t)(cells * 8);

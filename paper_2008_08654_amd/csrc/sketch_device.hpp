@@ -228,22 +228,24 @@ __device__ __forceinline__ void load_tile(const KeyT* __restrict__ keys, const W
   }
 }
 
-// Keys and weights at kp[j * 64], wp[j * 64], j < kKpt (all in range): one
-// base address per array and immediate offsets; every load is issued before
-// any value is used (as in load_tile).  big: some weight is outside
-// (-2^15, 2^15); any_hi: the or of the keys' high words.
+// Issues the loads of keys and weights at kp[j * 64], wp[j * 64], j < kKpt (all
+// in range): one base address per array and immediate offsets.  The values
+// are used later (tile_unpack), so the loads stay in flight meanwhile.
 template <int kKpt, typename KeyT, typename WT>
-__device__ __forceinline__ void load_tile_full(const KeyT* __restrict__ kp, const WT* __restrict__ wp,
-                                               uint32_t (&x0)[kKpt], uint32_t (&x1)[kKpt], int32_t (&wf)[kKpt],
-                                               bool& big, uint32_t& any_hi) {
-  KeyT kr[kKpt];
-  WT wr[kKpt];
+__device__ __forceinline__ void tile_issue(const KeyT* __restrict__ kp, const WT* __restrict__ wp, KeyT (&kr)[kKpt],
+                                           WT (&wr)[kKpt]) {
 #pragma unroll
   for (int j = 0; j < kKpt; ++j) {
     kr[j] = kp[j * 64];
     wr[j] = wp[j * 64];
   }
-  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Splits loaded keys into 32-bit limbs and weights into 32 bits.  big: some
+// weight is outside (-2^15, 2^15); any_hi: the or of the keys' high words.
+template <int kKpt, typename KeyT, typename WT>
+__device__ __forceinline__ void tile_unpack(const KeyT (&kr)[kKpt], const WT (&wr)[kKpt], uint32_t (&x0)[kKpt],
+                                            uint32_t (&x1)[kKpt], int32_t (&wf)[kKpt], bool& big, uint32_t& any_hi) {
 #pragma unroll
   for (int j = 0; j < kKpt; ++j) {
     const uint64_t k = (uint64_t)kr[j];
@@ -470,65 +472,104 @@ __device__ __forceinline__ void rows_tile(const RowArgs<KeyT, WT>& args, uint32_
   }
 }
 
+// One wave tile (64 * kRowKpt keys from `base`) of the rows of the block's
+// group; returns domain-error bits.
+template <int PRIME, int MODE, int K, int NP, typename KeyT, typename WT>
+__device__ __forceinline__ uint32_t rows_wave_tile(const RowArgs<KeyT, WT>& args, uint32_t r0, uint32_t* words,
+                                                   uint64_t base, uint32_t lane) {
+  uint32_t bad = 0;
+  if (base + 64 * kRowKpt <= args.n) {  // a full wave tile (wave-uniform)
+    uint32_t x0[kRowKpt], x1[kRowKpt];
+    int32_t wf[kRowKpt];
+    bool big = false;
+    uint32_t any_hi = 0;
+    KeyT pk[kRowKpt];
+    WT pw[kRowKpt];
+    tile_issue<kRowKpt>(args.keys + base + lane, args.weights + base + lane, pk, pw);
+    __builtin_amdgcn_sched_barrier(0);
+    tile_unpack<kRowKpt>(pk, pw, x0, x1, wf, big, any_hi);
+    if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;  // key >= 2^60 breaks p >= 2u - 1
+    if (!__any(big)) {  // every weight fits a field: no per-key selects
+      const int64_t* nowv = nullptr;
+      const bool* noesc = nullptr;
+      if (PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0)) {
+        rows_tile<PRIME, MODE, K, NP, true, false>(args, r0, words, x0, x1, wf, nowv, noesc, false);
+      } else {
+        uint32_t z[kRowKpt];  // the one-limb hash reads no high words
+#pragma unroll
+        for (int j = 0; j < kRowKpt; ++j) z[j] = 0;
+        rows_tile<PRIME, MODE, K, NP, false, false>(args, r0, words, x0, z, wf, nowv, noesc, false);
+      }
+      return bad;
+    }
+    // rare: a weight beyond the fields; the tile is loaded again below
+  }
+  uint32_t x0[kRowKpt], x1[kRowKpt];
+  int64_t wv[kRowKpt];
+  bool ok[kRowKpt];
+  int32_t wf[kRowKpt];
+  bool esc[kRowKpt];
+  load_tile<kRowKpt>(args.keys, args.weights, base, 64, lane, args.n, x0, x1, wv, ok);
+  uint32_t any_hi = 0;
+  bool any_e = false;
+#pragma unroll
+  for (int j = 0; j < kRowKpt; ++j) {
+    any_hi |= x1[j];
+    const bool fits = wv[j] > -32768 && wv[j] < 32768;
+    wf[j] = ok[j] && fits ? (int32_t)wv[j] : 0;  // positions past n add 0
+    esc[j] = ok[j] && !fits;
+    any_e |= esc[j];
+  }
+  if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;
+  const bool any_esc = __any(any_e);
+  if (PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0))
+    rows_tile<PRIME, MODE, K, NP, true, true>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
+  else
+    rows_tile<PRIME, MODE, K, NP, false, true>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
+  return bad;
+}
+
+// The wave tiles are cut into `xcds` contiguous ranges, one per XCD, and every
+// (range, row group) pair has a queue: a counter of taken chunks of kRowChunk
+// wave tiles.  A wave takes chunks for its block's group from its own XCD's
+// range first, so the nine (or however many) groups read each tile through
+// the same L2, then from the other ranges in turn until all are empty.  Every
+// wave tile of every group is taken exactly once (the counters are zero at
+// launch).  No wave waits for another.
 template <int PRIME, int MODE, int K, typename KeyT, typename WT>
 __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> args) {
   // static, so that LDS addresses need no base: one block per CU holds it all
   __shared__ __align__(16) uint32_t words[kRowLdsBytes / 4];
   constexpr int NP = MODE == kTwoPoly ? 2 : 1;
   const uint32_t G = args.groups;
-  const uint32_t g = blockIdx.x % G, rank = blockIdx.x / G;
-  const uint32_t cnt = (gridDim.x - g + G - 1) / G;  // blocks of group g
+  const uint32_t g = blockIdx.x % G;
   const uint32_t r0 = g * args.rpg;
   const uint32_t nwords = args.rpg << (args.log2m - 1);
   for (uint32_t i = threadIdx.x; i < nwords; i += kRowBlock) words[i] = 0x80008000u;
   __syncthreads();
-  const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t xcc;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+  const uint32_t X = args.xcds, home = (xcc & 15u) % X;
+  const uint64_t W = (args.n + 64 * kRowKpt - 1) / (64 * kRowKpt);  // wave tiles
   uint32_t bad = 0;
-  for (uint32_t t = rank; t < args.tiles; t += cnt) {
-    // wave `wave` takes keys [base, base + 64 * kRowKpt) of the tile
-    const uint64_t base = (uint64_t)t * kRowTile + (uint64_t)wave * (64 * kRowKpt);
-    if (base >= args.n) continue;
-    if (base + 64 * kRowKpt <= args.n) {  // a full wave tile (wave-uniform)
-      uint32_t x0[kRowKpt], x1[kRowKpt];
-      int32_t wf[kRowKpt];
-      bool big = false;
-      uint32_t any_hi = 0;
-      load_tile_full<kRowKpt>(args.keys + base + lane, args.weights + base + lane, x0, x1, wf, big, any_hi);
-      if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;  // key >= 2^60 breaks p >= 2u - 1
-      if (!__any(big)) {  // every weight fits a field: no per-key selects
-        const int64_t* nowv = nullptr;
-        const bool* noesc = nullptr;
-        if (PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0)) {
-          rows_tile<PRIME, MODE, K, NP, true, false>(args, r0, words, x0, x1, wf, nowv, noesc, false);
-        } else {
-          rows_tile<PRIME, MODE, K, NP, false, false>(args, r0, words, x0, x1, wf, nowv, noesc, false);
-        }
-        continue;
-      }
-      // rare: a weight beyond the fields; the tile is loaded again below
+  for (uint32_t k = 0; k < X; ++k) {
+    const uint32_t x = home + k < X ? home + k : home + k - X;
+    const uint64_t lo = W * x / X, hi = W * (x + 1) / X;
+    uint32_t* const q = args.queues + x * G + g;
+    // the next chunk is taken before the current one is processed, so the
+    // atomic's round trip overlaps the hashing
+    uint32_t next = 0;
+    if (lane == 0) next = atomicAdd(q, 1u);
+    for (;;) {
+      const uint32_t c = __builtin_amdgcn_readfirstlane(next);
+      const uint64_t wt0 = lo + (uint64_t)c * kRowChunk;
+      if (wt0 >= hi) break;
+      if (lane == 0) next = atomicAdd(q, 1u);
+      const uint64_t wt1 = wt0 + kRowChunk < hi ? wt0 + kRowChunk : hi;
+      for (uint64_t wt = wt0; wt < wt1; ++wt)
+        bad |= rows_wave_tile<PRIME, MODE, K, NP>(args, r0, words, wt * (64 * kRowKpt), lane);
     }
-    uint32_t x0[kRowKpt], x1[kRowKpt];
-    int64_t wv[kRowKpt];
-    bool ok[kRowKpt];
-    int32_t wf[kRowKpt];
-    bool esc[kRowKpt];
-    load_tile<kRowKpt>(args.keys, args.weights, base, 64, lane, args.n, x0, x1, wv, ok);
-    uint32_t any_hi = 0;
-    bool any_e = false;
-#pragma unroll
-    for (int j = 0; j < kRowKpt; ++j) {
-      any_hi |= x1[j];
-      const bool fits = wv[j] > -32768 && wv[j] < 32768;
-      wf[j] = ok[j] && fits ? (int32_t)wv[j] : 0;  // positions past n add 0
-      esc[j] = ok[j] && !fits;
-      any_e |= esc[j];
-    }
-    if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;
-    const bool any_esc = __any(any_e);
-    if (PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0))
-      rows_tile<PRIME, MODE, K, NP, true, true>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
-    else
-      rows_tile<PRIME, MODE, K, NP, false, true>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
   }
   if (bad) atomicOr(args.flags, kFlagDomain);
   __syncthreads();
@@ -1271,7 +1312,10 @@ hipError_t launch_update_t(const UpdatePlan& plan, const UpdateArgs<KeyT, WT>& a
   }
   if (plan.variant == kVariantRows) {
     RowArgs<KeyT, WT> r{a.keys, a.weights, a.n, a.coeffs, a.rows, a.log2m, plan.rpg, a.rows / plan.rpg,
-                        plan.tiles, a.table, a.flags};
+                        plan.tiles, a.table, a.flags, plan.queues, kRowXcds};
+    // the queues start at zero (a fill kernel: no memset node in a captured graph)
+    hipError_t ez = launch_fill_zero((unsigned long long*)plan.queues, kRowXcds * kMaxRows / 2, st);
+    if (ez != hipSuccess) return ez;
     hipLaunchKernelGGL((k_update_rows<PRIME, MODE, K, KeyT, WT>), dim3(plan.blocks), dim3(kRowBlock), 0, st, r);
     return hipGetLastError();
   }

@@ -39,6 +39,8 @@ constexpr int kRowKpt = 8;                          // keys per thread per tile
 constexpr uint32_t kRowTile = kRowBlock * kRowKpt;  // keys per tile
 constexpr uint32_t kRowMaxLog2m = 16;               // a row of 16-bit fields fits LDS
 constexpr uint32_t kRowLdsBytes = 160 * 1024;       // LDS a block may hold
+constexpr uint32_t kRowChunk = 8;                   // wave tiles a wave takes from a queue at once
+constexpr uint32_t kRowXcds = 8;                    // XCDs of the GPU: key ranges and queues per row group
 
 // two-pass (binned) update
 constexpr int kBinKpt = 8;                          // keys per thread in a pass-1 tile
@@ -70,11 +72,12 @@ struct UpdatePlan {
   uint32_t* desc;       // [tiles][rows][G + 1]
   // row-resident variant
   uint32_t rpg;         // rows per row group (a divisor of rows)
+  uint32_t* queues;     // kRowXcds * kMaxRows work-queue counters (the sketch's)
 };
 
 // Row-resident update: block b holds the 16-bit fields of row group b mod
-// groups (rpg rows of 2^log2m buckets) and takes the tiles rank, rank + cnt,
-// ... (rank = b / groups, cnt = blocks of its group).
+// groups (rpg rows of 2^log2m buckets); its waves take wave tiles from the
+// queues of that group, their own XCD's key range first.
 template <typename KeyT, typename WT>
 struct RowArgs {
   const KeyT* keys;
@@ -88,6 +91,8 @@ struct RowArgs {
   uint32_t tiles;
   unsigned long long* table;
   uint32_t* flags;
+  uint32_t* queues;  // xcds * groups counters, zero at launch
+  uint32_t xcds;
 };
 
 template <typename KeyT, typename WT>
