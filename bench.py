@@ -318,7 +318,8 @@ def run_batched(args):
     chosen = batch.autotune(stream)
     t_tune = time.perf_counter() - t_tune
     _log(f"batched: autotuned in {t_tune:.1f} s -> lds_table_max {chosen.lds_table_max}, "
-         f"chunk {chosen.lds_chunk_keys}, combine {chosen.combine}, direct {chosen.direct_fraction}")
+         f"chunk {chosen.lds_chunk_keys}, combine {chosen.combine}, direct {chosen.direct_fraction}, "
+         f"keys/thread {chosen.keys_per_thread or 8}, row-resident {chosen.row_resident}")
 
     def timed(fn, steps):
         for _ in range(args.warmup):
@@ -350,16 +351,18 @@ def run_batched(args):
     plain_wall_ms = plain_elapsed * 1e3 / max(1, args.steps // 4)
     ops_key = 5 * OPS_PER_KEY_ROW[("p61", 0)] + OPS_PER_KEY
     achieved = ops_key * total / (batch_ms * 1e-3) / 1e12
-    ng, nl, nt = batch.classes()
+    ng, nl, nr, nt = batch.classes()
     out = {"metric": "aggregate Gkeys/s into 4096 Count Sketches (p=2^61-1, 4-universal), one batched update",
            "value": round(total * args.steps / elapsed / 1e9, 3), "unit": "Gkeys/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
            "config": {"workload": "batched", "sketches": count, "keys": total, "rows": 5,
                       "buckets": "2^8..2^16 log-uniform", "classes": {"direct_atomics": ng, "lds": nl,
-                                                                      "two_pass": nt},
+                                                                      "row_resident": nr, "two_pass": nt},
                       "autotuned": {"lds_table_max": chosen.lds_table_max, "lds_chunk_keys": chosen.lds_chunk_keys,
-                                    "combine": chosen.combine, "direct_fraction": chosen.direct_fraction},
+                                    "combine": chosen.combine, "direct_fraction": chosen.direct_fraction,
+                                    "keys_per_thread": chosen.keys_per_thread or 8,
+                                    "row_resident": chosen.row_resident},
                       "autotune_s": round(t_tune, 2),
                       "plain_launches_ms": round(plain_wall_ms, 3),
                       "plain_gkeys_per_s": round(total / (plain_wall_ms * 1e-3) / 1e9, 3),

@@ -73,7 +73,7 @@ def lib() -> ctypes.CDLL:
             "cs_batch_update": [P, P],
             "cs_batch_autotune": [P, P, P],
             "cs_batch_get_options": [P, P],
-            "cs_batch_classes": [P, P, P, P],
+            "cs_batch_classes": [P, P, P, P, P],
             "cs_server_create": [i32, i32, u32, i32, i32, P, P],
             "cs_server_admit": [P, u32, u64, u64, P],
             "cs_server_evict": [P, u32],
@@ -258,7 +258,8 @@ class _BatchItem(ctypes.Structure):
 
 class BatchOptions(ctypes.Structure):
     _fields_ = [("lds_table_max", ctypes.c_uint32), ("lds_chunk_keys", ctypes.c_uint32),
-                ("combine", ctypes.c_int), ("use_graph", ctypes.c_int), ("direct_fraction", ctypes.c_double)]
+                ("combine", ctypes.c_int), ("use_graph", ctypes.c_int), ("direct_fraction", ctypes.c_double),
+                ("keys_per_thread", ctypes.c_uint32), ("row_resident", ctypes.c_int)]
 
 
 class Batch:
@@ -305,10 +306,11 @@ class Batch:
         _check(lib().cs_batch_get_options(self._h, ctypes.byref(out)))
         return out
 
-    def classes(self) -> tuple[int, int, int]:
-        a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
-        _check(lib().cs_batch_classes(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return a.value, b.value, c.value
+    def classes(self) -> tuple[int, int, int, int]:
+        """Members per class: (direct atomics, LDS, row-resident, two-pass)."""
+        a, b, c, d = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().cs_batch_classes(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
 
     def close(self):
         if self._h:

@@ -28,7 +28,7 @@ struct cs_batch {
   size_t work_bytes = 0;
   std::vector<BatchRound> rounds;
   BatchLaunch launch{};
-  uint32_t n_global = 0, n_lds = 0, n_twopass = 0;
+  uint32_t n_global = 0, n_lds = 0, n_rows = 0, n_twopass = 0;
   bool planned = false;
   // graph
   hipStream_t cap_stream = nullptr;
@@ -69,6 +69,15 @@ cs_status mcs::batch_plan(const cs_batch_item* items, size_t count, int kb, int 
   const uint64_t chunk = opts.lds_chunk_keys ? opts.lds_chunk_keys : kDefaultChunk;
   P.combine = opts.combine >= 0;
   const double direct = opts.direct_fraction == 0.0 ? kDefaultDirect : opts.direct_fraction;
+  const bool rows_on = opts.row_resident >= 0;
+  if (opts.keys_per_thread != 0 && opts.keys_per_thread != 4 && opts.keys_per_thread != 8)
+    return fail(CS_EINVAL, "keys_per_thread must be 0, 4 or 8");
+  P.row_kpt = opts.keys_per_thread ? (int)opts.keys_per_thread : 8;
+  struct RowMember {
+    uint32_t id, rpg, rows, log2m;
+    uint64_t n;
+  };
+  std::vector<RowMember> row_members;
   std::vector<uint64_t> round_keys(1, 0);
   std::vector<size_t> round_bytes(1, 0);
   P.round_tiles.assign(1, 0);
@@ -81,11 +90,16 @@ cs_status mcs::batch_plan(const cs_batch_item* items, size_t count, int kb, int 
     const uint64_t cells = (uint64_t)s->rows << s->log2m;
     BatchSketch bs{it.keys, it.weights, it.n, (const uint4*)s->d_coeffs, (unsigned long long*)s->d_table,
                    s->d_flags, s->rows, s->log2m};
+    const uint32_t rpg = rows_on ? rows_per_group(s->rows, s->log2m) : 0;
     if (direct > 0.0 && (double)it.n < direct * (double)m) {  // fewer updates than a flush would touch
       const uint32_t id = (uint32_t)P.sks.size();
       P.sks.push_back(bs);
-      for (uint64_t o = 0; o < it.n; o += kGlobalChunk)
-        P.glb_items.push_back(BatchLdsItem{id, 0, o, std::min(it.n, o + kGlobalChunk)});
+      if (rows_on) {
+        row_members.push_back(RowMember{id, 0, s->rows, s->log2m, it.n});
+      } else {
+        for (uint64_t o = 0; o < it.n; o += kGlobalChunk)
+          P.glb_items.push_back(BatchLdsItem{id, 0, o, std::min(it.n, o + kGlobalChunk)});
+      }
       ++P.n_global;
     } else if (cells * 8 <= lds_max) {
       const uint32_t id = (uint32_t)P.sks.size();
@@ -94,6 +108,11 @@ cs_status mcs::batch_plan(const cs_batch_item* items, size_t count, int kb, int 
       for (uint64_t o = 0; o < it.n; o += c) P.lds_items.push_back(BatchLdsItem{id, 0, o, std::min(it.n, o + c)});
       P.max_table = std::max<uint32_t>(P.max_table, (uint32_t)(cells * 8));
       ++P.n_lds;
+    } else if (rpg) {
+      const uint32_t id = (uint32_t)P.sks.size();
+      P.sks.push_back(bs);
+      row_members.push_back(RowMember{id, rpg, s->rows, s->log2m, it.n});
+      ++P.n_rows;
     } else {
       uint32_t log2g, log2r;
       if (!batch_twopass_shape(s->rows, s->log2m, &log2g, &log2r))
@@ -139,6 +158,39 @@ cs_status mcs::batch_plan(const cs_batch_item* items, size_t count, int kb, int 
       ++P.n_twopass;
     }
   }
+  // Row items: each row group (or, for a direct member, the whole sketch) over
+  // ranges of wave tiles, cut so that no item holds more than about 1/6 of a
+  // CU's share of the batch's key-rows, then ordered largest first so that
+  // the persistent blocks finish together.
+  if (!row_members.empty()) {
+    const uint64_t wt_keys = 64ull * (uint64_t)P.row_kpt;
+    uint64_t total = 0;
+    for (const RowMember& r : row_members) total += r.n * r.rows;
+    const uint64_t target = std::max<uint64_t>(1ull << 18, total / ((uint64_t)lim.cus * 6));
+    struct Costed {
+      uint64_t cost;
+      BatchRowItem item;
+    };
+    std::vector<Costed> all;
+    for (const RowMember& r : row_members) {
+      const uint64_t tiles = (r.n + wt_keys - 1) / wt_keys;
+      const uint32_t per = r.rpg ? r.rpg : r.rows;     // rows an item adds a key to
+      const uint64_t groups = r.rpg ? r.rows / r.rpg : 1;
+      const uint64_t per_tile = wt_keys * per * (r.rpg ? 1 : 2);  // direct atomics cost about twice a field add
+      const uint64_t pieces = std::max<uint64_t>(1, std::min<uint64_t>((tiles + 15) / 16,
+                                                                         (tiles * per_tile + target - 1) / target));
+      const uint64_t fields = r.rpg ? ((uint64_t)r.rpg << r.log2m) / 4 : 0;  // clearing and flushing the fields
+      for (uint64_t g = 0; g < groups; ++g)
+        for (uint64_t pc = 0; pc < pieces; ++pc) {
+          const uint64_t b = tiles * pc / pieces, e = tiles * (pc + 1) / pieces;
+          all.push_back(Costed{(e - b) * per_tile + fields,
+                               BatchRowItem{r.id, (uint32_t)(g * r.rpg), r.rpg, 0, b, e}});
+        }
+    }
+    std::stable_sort(all.begin(), all.end(), [](const Costed& a, const Costed& b) { return a.cost > b.cost; });
+    P.row_items.reserve(all.size());
+    for (const Costed& c : all) P.row_items.push_back(c.item);
+  }
   for (size_t v : round_bytes) P.work_bytes = std::max(P.work_bytes, v);
   // segments are appended round by round, so each round's are contiguous
   const uint32_t nr = (uint32_t)round_keys.size();
@@ -165,7 +217,9 @@ cs_status mcs::batch_plan(const cs_batch_item* items, size_t count, int kb, int 
   P.o_glb = align256(P.o_lds + P.lds_items.size() * sizeof(BatchLdsItem));
   P.o_seg = align256(P.o_glb + P.glb_items.size() * sizeof(BatchLdsItem));
   P.o_acc = align256(P.o_seg + P.segs.size() * sizeof(BatchSegment));
-  P.lists_bytes = align256(P.o_acc + P.acc_items.size() * sizeof(BatchAccItem)) + 256;
+  P.o_row = align256(P.o_acc + P.acc_items.size() * sizeof(BatchAccItem));
+  P.o_queue = align256(P.o_row + P.row_items.size() * sizeof(BatchRowItem));
+  P.lists_bytes = P.o_queue + 256;
   return CS_OK;
 }
 
@@ -182,6 +236,7 @@ void mcs::batch_emit(BatchPlan& P, int prime, int mode, int k, int kb, int wb, c
     segs[i].desc = (uint32_t*)(d_work + P.segs[i].desc_off);
   }
   memcpy(host + P.o_acc, P.acc_items.data(), P.acc_items.size() * sizeof(BatchAccItem));
+  memcpy(host + P.o_row, P.row_items.data(), P.row_items.size() * sizeof(BatchRowItem));
   rounds->clear();
   for (uint32_t r = 0; r + 1 < P.seg_first.size(); ++r) {
     if (P.seg_first[r + 1] == P.seg_first[r]) continue;
@@ -223,6 +278,11 @@ void mcs::batch_emit(BatchPlan& P, int prime, int mode, int k, int kb, int wb, c
   L.bin_blocks = dev.cus * 8;
   L.acc_lds_bytes = acc_lds;
   L.acc_blocks = acc_max;
+  L.row_item_list = (const BatchRowItem*)(d_lists + P.o_row);
+  L.row_items = (uint32_t)P.row_items.size();
+  L.row_blocks = std::max<uint32_t>(1, std::min<uint32_t>(L.row_items, dev.cus));
+  L.row_queue = (uint32_t*)(d_lists + P.o_queue);
+  L.row_kpt = P.row_kpt;
 }
 
 namespace {
@@ -248,10 +308,12 @@ cs_status build_plan(cs_batch* b) {
   const DeviceInfo& dev = device_info(b->device);
   BatchPlan P;
   BatchPlanLimits lim;
+  lim.cus = (uint32_t)dev.cus;
   cs_status st = batch_plan(b->items.data(), b->items.size(), b->kb, b->wb, b->opts, lim, &P);
   if (st != CS_OK) return st;
   b->n_global = P.n_global;
   b->n_lds = P.n_lds;
+  b->n_rows = P.n_rows;
   b->n_twopass = P.n_twopass;
   if (P.work_bytes > b->work_bytes) {
     if (b->d_work) (void)hipFree(b->d_work);
@@ -358,61 +420,151 @@ extern "C" cs_status cs_batch_get_options(const cs_batch* b, cs_batch_options* o
   return CS_OK;
 }
 
-extern "C" cs_status cs_batch_classes(const cs_batch* b, uint32_t* n_global, uint32_t* n_lds, uint32_t* n_twopass) {
+extern "C" cs_status cs_batch_classes(const cs_batch* b, uint32_t* n_global, uint32_t* n_lds, uint32_t* n_rows,
+                                      uint32_t* n_twopass) {
   if (!b) return fail(CS_EINVAL, "batch is NULL");
   if (n_global) *n_global = b->n_global;
   if (n_lds) *n_lds = b->n_lds;
+  if (n_rows) *n_rows = b->n_rows;
   if (n_twopass) *n_twopass = b->n_twopass;
   return CS_OK;
 }
 
+namespace {
+
+// A copy of every member's counters and flags in one device buffer, so that
+// tuning trials leave the sketches as they were.
+struct SavedTables {
+  char* buf = nullptr;
+  std::vector<std::pair<cs_sketch*, size_t>> at;  // sketch, offset of its table copy
+};
+
+size_t table_bytes(const cs_sketch* s) { return ((size_t)s->rows << s->log2m) * sizeof(int64_t); }
+
+cs_status save_tables(const cs_batch* b, hipStream_t stream, SavedTables* sv) {
+  std::vector<cs_sketch*> sks;
+  for (const cs_batch_item& it : b->items) sks.push_back(it.sketch);
+  std::sort(sks.begin(), sks.end());
+  sks.erase(std::unique(sks.begin(), sks.end()), sks.end());
+  size_t bytes = 0;
+  for (cs_sketch* s : sks) {
+    sv->at.emplace_back(s, bytes);
+    bytes = align256(bytes + table_bytes(s) + sizeof(uint32_t));
+  }
+  hipError_t e = hipMalloc(&sv->buf, std::max<size_t>(bytes, 256));
+  if (e != hipSuccess) {
+    sv->buf = nullptr;
+    (void)hipGetLastError();
+    return fail(status_of(e), "autotune: %zu bytes of device memory to keep the members' counters", bytes);
+  }
+  for (const auto& [s, off] : sv->at) {
+    e = hipMemcpyAsync(sv->buf + off, s->d_table, table_bytes(s), hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(sv->buf + off + table_bytes(s), s->d_flags, sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                         stream);
+    if (e != hipSuccess) return hip_fail(e, "autotune: copying the members' counters");
+  }
+  return CS_OK;
+}
+
+cs_status restore_tables(SavedTables* sv, hipStream_t stream) {
+  cs_status st = CS_OK;
+  if (!sv->buf) return st;
+  for (const auto& [s, off] : sv->at) {
+    hipError_t e = hipMemcpyAsync(s->d_table, sv->buf + off, table_bytes(s), hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->d_flags, sv->buf + off + table_bytes(s), sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                         stream);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "autotune: restoring the members' counters");
+      break;
+    }
+  }
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess && st == CS_OK) st = hip_fail(e, "autotune: restoring the members' counters");
+  (void)hipFree(sv->buf);
+  sv->buf = nullptr;
+  return st;
+}
+
+}  // namespace
+
 extern "C" cs_status cs_batch_autotune(cs_batch* b, hipStream_t stream, cs_batch_options* chosen) {
   if (!b) return fail(CS_EINVAL, "batch is NULL");
   const cs_batch_options keep = b->opts;
-  std::vector<cs_batch_options> cands;
-  // LDS limits from "no table in LDS" (8 bytes: repeated keys then meet the
-  // two-pass update's combining) to the largest table LDS holds
-  for (uint32_t lm : {8u, 20480u, 40960u, 65536u, 163840u})
-    for (uint32_t ch : {1u << 15, 1u << 17})
-      for (int cb : {1, -1})
-        for (double df : {1.0 / 128, 0.125, 1.0}) cands.push_back(cs_batch_options{lm, ch, cb, keep.use_graph, df});
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-    return fail(CS_EDEVICE, "event creation");
+  SavedTables saved;
+  cs_status status = save_tables(b, stream, &saved);
+  if (status != CS_OK) {
+    (void)restore_tables(&saved, stream);
+    return status;
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+    status = fail(CS_EDEVICE, "event creation");
+  }
+  // median of three timed updates after one warm-up
+  auto measure = [&](const cs_batch_options& c, float* ms) -> cs_status {
+    b->opts = c;
+    cs_status st = build_plan(b);
+    if (st == CS_OK) st = run_plan(b, stream, false);
+    float t[3] = {0, 0, 0};
+    for (int i = 0; i < 3 && st == CS_OK; ++i) {
+      if (hipEventRecord(ev[0], stream) != hipSuccess) st = fail(CS_EDEVICE, "autotune timing");
+      if (st == CS_OK) st = run_plan(b, stream, false);
+      if (st == CS_OK && (hipEventRecord(ev[1], stream) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                          hipEventElapsedTime(&t[i], ev[0], ev[1]) != hipSuccess))
+        st = fail(CS_EDEVICE, "autotune timing");
+    }
+    std::sort(t, t + 3);
+    *ms = t[1];
+    return st;
+  };
   float best = 1e30f;
   cs_batch_options best_opts = keep;
-  cs_status status = CS_OK;
-  for (const cs_batch_options& c : cands) {
-    b->opts = c;
-    status = build_plan(b);
-    if (status != CS_OK) break;
-    status = run_plan(b, stream, false);  // warm-up
-    if (status != CS_OK) break;
-    hipEventRecord(e0, stream);
-    status = run_plan(b, stream, false);
-    if (status != CS_OK) break;
-    hipEventRecord(e1, stream);
-    if (hipEventSynchronize(e1) != hipSuccess) {
-      status = fail(CS_EDEVICE, "autotune timing");
-      break;
-    }
+  auto consider = [&](const cs_batch_options& c) {
+    if (status != CS_OK) return;
     float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best) {
+    status = measure(c, &ms);
+    if (status == CS_OK && ms < best) {
       best = ms;
       best_opts = c;
     }
+  };
+  // the class limits, every combination
+  for (int rr : {1, -1})
+    for (uint32_t lm : {8u, 20480u, 40960u, 65536u, 163840u})
+      for (double df : {1.0 / 128, 0.125, 1.0}) {
+        cs_batch_options c{};
+        c.lds_table_max = lm;
+        c.use_graph = keep.use_graph;
+        c.direct_fraction = df;
+        c.row_resident = rr;
+        consider(c);
+      }
+  // then one knob at a time from the best so far
+  for (uint32_t kpt : {4u, 8u}) {
+    cs_batch_options c = best_opts;
+    c.keys_per_thread = kpt;
+    consider(c);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  for (uint32_t ch : {1u << 15, 1u << 17}) {
+    cs_batch_options c = best_opts;
+    c.lds_chunk_keys = ch;
+    consider(c);
+  }
+  for (int cb : {1, -1}) {
+    cs_batch_options c = best_opts;
+    c.combine = cb;
+    consider(c);
+  }
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
   b->opts = status == CS_OK ? best_opts : keep;
   cs_status st2 = build_plan(b);
   if (status == CS_OK) status = st2;
-  // the trial runs added into the tables: zero them
-  for (const cs_batch_item& it : b->items) {
-    if (cs_reset(it.sketch, stream) != CS_OK && status == CS_OK) status = CS_EDEVICE;
-  }
-  if (hipStreamSynchronize(stream) != hipSuccess && status == CS_OK) status = fail(CS_EDEVICE, "autotune sync");
+  // the trials added into the tables: put back what they held
+  st2 = restore_tables(&saved, stream);
+  if (status == CS_OK) status = st2;
   if (chosen) *chosen = b->opts;
   return status;
 }

@@ -321,7 +321,7 @@ static bool binned_fits(const cs_sketch* s, uint32_t* log2g, uint32_t* log2r) {
 
 // Rows per row group of the row-resident update: the largest divisor of rows
 // whose 16-bit fields fit the block's LDS (0 if not even one row fits).
-static uint32_t rows_per_group(uint32_t rows, uint32_t log2m) {
+uint32_t mcs::rows_per_group(uint32_t rows, uint32_t log2m) {
   if (log2m > kRowMaxLog2m) return 0;
   const uint32_t fit = (uint32_t)(kRowLdsBytes / (2ull << log2m));
   for (uint32_t r = std::min(rows, fit); r >= 1; --r)

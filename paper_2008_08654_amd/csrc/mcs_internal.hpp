@@ -53,6 +53,10 @@ cs_status status_of(hipError_t e);
 // Sets the last-error message and returns status_of(e) (never CS_OK).
 cs_status hip_fail(hipError_t e, const char* what);
 
+// Rows per row group of the row-resident update: the largest divisor of rows
+// whose 16-bit fields (rpg * 2^log2m * 2 bytes) fit a block's LDS; 0 when no
+// row fits (more than 2^16 buckets).
+uint32_t rows_per_group(uint32_t rows, uint32_t log2m);
 UpdatePlan plan_update(const cs_sketch* s, uint64_t n);
 // Enqueues the plan's launches; the two-pass path runs in rounds as large as
 // `work` (work_bytes) holds.  Allocates nothing.
@@ -79,6 +83,7 @@ size_t sketch_device_bytes(uint32_t rows, uint32_t log2m, cs_mode mode, uint32_t
 struct BatchPlanLimits {
   uint64_t round_keys = 1ull << 27;  // keys of two-pass segments per round
   size_t work_cap = ~(size_t)0;      // workspace bytes per round
+  uint32_t cus = 256;                // compute units: row items are sized for this many blocks
 };
 
 struct BatchPlan {
@@ -91,14 +96,16 @@ struct BatchPlan {
   std::vector<BatchLdsItem> lds_items, glb_items;
   std::vector<Seg> segs;  // in round order
   std::vector<BatchAccItem> acc_items;
+  std::vector<BatchRowItem> row_items;  // row-resident and direct items, largest first
+  uint32_t row_kpt = 8;
   std::vector<uint32_t> seg_first, acc_first;  // per round, plus one past the end
   std::vector<uint32_t> round_tiles;
   uint32_t max_table = 0, max_span = 0, max_wave_lds = 0;
   bool combine = true;
-  uint32_t n_global = 0, n_lds = 0, n_twopass = 0;
+  uint32_t n_global = 0, n_lds = 0, n_rows = 0, n_twopass = 0;
   size_t work_bytes = 0;   // workspace the largest round needs
   size_t lists_bytes = 0;  // bytes of the device work lists
-  size_t o_sk = 0, o_lds = 0, o_glb = 0, o_seg = 0, o_acc = 0;
+  size_t o_sk = 0, o_lds = 0, o_glb = 0, o_seg = 0, o_acc = 0, o_row = 0, o_queue = 0;
 };
 
 bool batch_twopass_shape(uint32_t rows, uint32_t log2m, uint32_t* log2g, uint32_t* log2r);

@@ -231,6 +231,7 @@ void launch_step(cs_server* S, Step& st) {
   if (!items.empty()) {
     BatchPlanLimits lim;
     lim.work_cap = S->work_bytes;
+    lim.cus = (uint32_t)device_info(S->device).cus;
     cs_batch_options opts{};
     opts.direct_fraction = S->direct_fraction;
     st.status = batch_plan(items.data(), items.size(), S->kb, S->wb, opts, lim, &P);

@@ -411,26 +411,28 @@ __global__ __launch_bounds__(kBlock) void k_update_global(UpdateArgs<KeyT, WT> a
 // The rows of a row group for one wave's keys: hash, add each s*w into its
 // field, carry wraps into the global counters.  ESC: some keys have weights
 // that bypass the fields (esc[j]); without ESC every wf[j] is the key's weight.
-template <int PRIME, int MODE, int K, int NP, bool WIDE, bool ESC, typename KeyT, typename WT>
-__device__ __forceinline__ void rows_tile(const RowArgs<KeyT, WT>& args, uint32_t r0, uint32_t* words,
-                                          const uint32_t (&x0)[kRowKpt], const uint32_t (&x1)[kRowKpt],
-                                          const int32_t (&wf)[kRowKpt], const int64_t* wv, const bool* esc,
-                                          bool any_esc) {
+// One row (local index r of the block's group, global index row, coefficients
+// c) for one wave's keys.
+template <int PRIME, int MODE, int K, int NP, bool WIDE, bool ESC, int NK, typename KeyT, typename WT>
+__device__ __forceinline__ void row_update(const RowArgs<KeyT, WT>& args, const RowCoeffs<K, NP>& c, uint32_t row,
+                                           uint32_t r, uint32_t* words, const uint32_t (&x0)[NK],
+                                           const uint32_t (&x1)[NK], const int32_t (&wf)[NK],
+                                           const int64_t* wv, const bool* esc, bool any_esc) {
   const uint32_t m = 1u << args.log2m;
   const uint32_t amask = 2u * m - 4u;  // byte offset of a bucket's word in its row: code & amask
-  for (uint32_t r = 0; r < args.rpg; ++r) {
-    const uint32_t row = r0 + r;
-    const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)row * NP * K);
+  {
     // byte offset of the row in LDS, a multiple of 2m, or-ed onto code & amask;
     // kept in a vector register so that the and-or takes one instruction
     uint32_t rowoff;
     asm volatile("v_mov_b32 %0, %1" : "=v"(rowoff) : "s"(r * 2u * m));
-    uint32_t code[kRowKpt], old[kRowKpt], sh[kRowKpt];
-    int32_t sw[kRowKpt];
+    uint32_t code[NK], old[NK], sh[NK];
+    int32_t sw[NK];
+    {
 #pragma unroll
-    for (int j = 0; j < kRowKpt; ++j) code[j] = bucket_code<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m);
+      for (int j = 0; j < NK; ++j) code[j] = bucket_code<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m);
+    }
 #pragma unroll
-    for (int j = 0; j < kRowKpt; ++j) {
+    for (int j = 0; j < NK; ++j) {
       // s * w with s = 1 - 2a, a = bit 0 of the code; the field's half is bit 0
       // of the bucket (bit 1 of the code)
       const int32_t sgn = __builtin_amdgcn_sbfe((int)code[j], 0, 1);
@@ -438,10 +440,10 @@ __device__ __forceinline__ void rows_tile(const RowArgs<KeyT, WT>& args, uint32_
       sh[j] = (code[j] & 2u) << 3;
       old[j] = atomicAdd((uint32_t*)((unsigned char*)words + ((code[j] & amask) | rowoff)), (uint32_t)sw[j] << sh[j]);
     }
-    bool wr[kRowKpt];
+    bool wr[NK];
     bool any_wr = false;
 #pragma unroll
-    for (int j = 0; j < kRowKpt; ++j) {
+    for (int j = 0; j < NK; ++j) {
       const int32_t t = (int32_t)__builtin_amdgcn_ubfe(old[j], sh[j], 16u) + sw[j];
       wr[j] = (uint32_t)t > 0xFFFFu;
       any_wr |= wr[j];
@@ -449,7 +451,7 @@ __device__ __forceinline__ void rows_tile(const RowArgs<KeyT, WT>& args, uint32_
     unsigned long long* const grow = args.table + ((size_t)row << args.log2m);
     if (__any(any_wr)) {
 #pragma unroll
-      for (int j = 0; j < kRowKpt; ++j)
+      for (int j = 0; j < NK; ++j)
         if (wr[j]) {
           const uint32_t bucket = (code[j] >> 1) & (m - 1u);
           const int32_t t = (int32_t)__builtin_amdgcn_ubfe(old[j], sh[j], 16u) + sw[j];
@@ -463,7 +465,7 @@ __device__ __forceinline__ void rows_tile(const RowArgs<KeyT, WT>& args, uint32_
     }
     if (ESC && any_esc) {
 #pragma unroll
-      for (int j = 0; j < kRowKpt; ++j)
+      for (int j = 0; j < NK; ++j)
         if (esc[j]) {
           const uint32_t bucket = (code[j] >> 1) & (m - 1u);
           atomicAdd(&grow[bucket], signed_weight(wv[j], code[j] & 1u));
@@ -472,61 +474,106 @@ __device__ __forceinline__ void rows_tile(const RowArgs<KeyT, WT>& args, uint32_
   }
 }
 
-// One wave tile (64 * kRowKpt keys from `base`) of the rows of the block's
-// group; returns domain-error bits.
-template <int PRIME, int MODE, int K, int NP, typename KeyT, typename WT>
-__device__ __forceinline__ uint32_t rows_wave_tile(const RowArgs<KeyT, WT>& args, uint32_t r0, uint32_t* words,
-                                                   uint64_t base, uint32_t lane) {
+// The rows of the block's group for one wave's keys.
+template <int PRIME, int MODE, int K, int NP, bool WIDE, bool ESC, int NK, typename KeyT, typename WT>
+__device__ __forceinline__ void rows_tile(const RowArgs<KeyT, WT>& args, uint32_t r0, uint32_t* words,
+                                          const uint32_t (&x0)[NK], const uint32_t (&x1)[NK],
+                                          const int32_t (&wf)[NK], const int64_t* wv, const bool* esc,
+                                          bool any_esc) {
+  for (uint32_t r = 0; r < args.rpg; ++r) {
+    const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)(r0 + r) * NP * K);
+    row_update<PRIME, MODE, K, NP, WIDE, ESC, NK>(args, c, r0 + r, r, words, x0, x1, wf, wv, esc, any_esc);
+  }
+}
+
+// A wave tile (64 * KPT keys from `base`) of the rows of the block's group in
+// the general way: positions past n, weights that bypass the fields, keys of
+// two limbs; in two halves of KPT / 2 keys per lane, so that it needs few
+// registers.  Returns domain-error bits.
+template <int PRIME, int MODE, int K, int NP, int KPT, typename KeyT, typename WT>
+__device__ __forceinline__ uint32_t rows_wave_tile_slow(const RowArgs<KeyT, WT>& args, uint32_t r0, uint32_t* words,
+                                                        uint64_t base, uint32_t lane) {
+  constexpr int NK = KPT / 2;
   uint32_t bad = 0;
-  if (base + 64 * kRowKpt <= args.n) {  // a full wave tile (wave-uniform)
-    uint32_t x0[kRowKpt], x1[kRowKpt];
-    int32_t wf[kRowKpt];
+  for (uint32_t h = 0; h < 2; ++h) {
+    const uint64_t hb = base + h * 64 * NK;
+    if (hb >= args.n) break;
+    uint32_t x0[NK], x1[NK];
+    int64_t wv[NK];
+    bool ok[NK];
+    int32_t wf[NK];
+    bool esc[NK];
+    load_tile<NK>(args.keys, args.weights, hb, 64, lane, args.n, x0, x1, wv, ok);
+    uint32_t any_hi = 0;
+    bool any_e = false;
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+      any_hi |= x1[j];
+      const bool fits = wv[j] > -32768 && wv[j] < 32768;
+      wf[j] = ok[j] && fits ? (int32_t)wv[j] : 0;  // positions past n add 0
+      esc[j] = ok[j] && !fits;
+      any_e |= esc[j];
+    }
+    if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;  // key >= 2^60 breaks p >= 2u - 1
+    const bool any_esc = __any(any_e);
+    if (PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0))
+      rows_tile<PRIME, MODE, K, NP, true, true, NK>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
+    else
+      rows_tile<PRIME, MODE, K, NP, false, true, NK>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
+  }
+  return bad;
+}
+
+// One wave tile `wt` (64 * KPT keys, loaded into kk, ww when the tile is full)
+// of the rows of the block's group (first row r0; c1 holds row r0's
+// coefficients, used when the group is that one row).  Common case: a full
+// tile whose keys have one limb (p61) and whose weights fit the fields; the
+// rest goes to the general path.  Returns domain-error bits.
+template <int PRIME, int MODE, int K, int NP, int KPT, typename KeyT, typename WT>
+__device__ __forceinline__ uint32_t rows_wave_tile(const RowArgs<KeyT, WT>& args, const RowCoeffs<K, NP>& c1, bool one,
+                                                   uint32_t r0, uint32_t* words, uint64_t wt,
+                                                   const KeyT (&kk)[KPT], const WT (&ww)[KPT], uint32_t lane) {
+  constexpr uint64_t kWt = 64 * KPT;
+  uint32_t bad = 0;
+  if ((wt + 1) * kWt <= args.n) {
+    uint32_t x0[KPT], x1[KPT];
+    int32_t wf[KPT];
     bool big = false;
     uint32_t any_hi = 0;
-    KeyT pk[kRowKpt];
-    WT pw[kRowKpt];
-    tile_issue<kRowKpt>(args.keys + base + lane, args.weights + base + lane, pk, pw);
-    __builtin_amdgcn_sched_barrier(0);
-    tile_unpack<kRowKpt>(pk, pw, x0, x1, wf, big, any_hi);
+    tile_unpack<KPT>(kk, ww, x0, x1, wf, big, any_hi);
     if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;  // key >= 2^60 breaks p >= 2u - 1
-    if (!__any(big)) {  // every weight fits a field: no per-key selects
-      const int64_t* nowv = nullptr;
-      const bool* noesc = nullptr;
-      if (PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0)) {
-        rows_tile<PRIME, MODE, K, NP, true, false>(args, r0, words, x0, x1, wf, nowv, noesc, false);
-      } else {
-        uint32_t z[kRowKpt];  // the one-limb hash reads no high words
+    const bool two_limb = PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0);
+    if (!two_limb && !__any(big)) {
+      if constexpr (PRIME == kPrime61) {
 #pragma unroll
-        for (int j = 0; j < kRowKpt; ++j) z[j] = 0;
-        rows_tile<PRIME, MODE, K, NP, false, false>(args, r0, words, x0, z, wf, nowv, noesc, false);
+        for (int j = 0; j < KPT; ++j) x1[j] = 0;  // the one-limb hash reads no high words
       }
+      if (one)
+        row_update<PRIME, MODE, K, NP, false, false, KPT>(args, c1, r0, 0, words, x0, x1, wf, nullptr, nullptr,
+                                                          false);
+      else
+        rows_tile<PRIME, MODE, K, NP, false, false, KPT>(args, r0, words, x0, x1, wf, nullptr, nullptr, false);
       return bad;
     }
-    // rare: a weight beyond the fields; the tile is loaded again below
   }
-  uint32_t x0[kRowKpt], x1[kRowKpt];
-  int64_t wv[kRowKpt];
-  bool ok[kRowKpt];
-  int32_t wf[kRowKpt];
-  bool esc[kRowKpt];
-  load_tile<kRowKpt>(args.keys, args.weights, base, 64, lane, args.n, x0, x1, wv, ok);
-  uint32_t any_hi = 0;
-  bool any_e = false;
-#pragma unroll
-  for (int j = 0; j < kRowKpt; ++j) {
-    any_hi |= x1[j];
-    const bool fits = wv[j] > -32768 && wv[j] < 32768;
-    wf[j] = ok[j] && fits ? (int32_t)wv[j] : 0;  // positions past n add 0
-    esc[j] = ok[j] && !fits;
-    any_e |= esc[j];
+  return bad | rows_wave_tile_slow<PRIME, MODE, K, NP, KPT, KeyT, WT>(args, r0, words, wt * kWt, lane);
+}
+
+// Adds field - 2^15 of every non-zero field of the block's group (rpg rows
+// from row r0, nwords LDS words) into the global counters; word i holds
+// buckets 2i and 2i + 1 of its row, so a wave's adds are contiguous.
+template <typename KeyT, typename WT>
+__device__ __forceinline__ void rows_flush(const RowArgs<KeyT, WT>& args, uint32_t r0, const uint32_t* words,
+                                           uint32_t nwords) {
+  const uint32_t lw = args.log2m - 1;
+  for (uint32_t i = threadIdx.x; i < nwords; i += kRowBlock) {
+    const uint32_t w = words[i];
+    const uint32_t r = i >> lw, wi = i & ((1u << lw) - 1u);
+    unsigned long long* const p = args.table + ((size_t)(r0 + r) << args.log2m) + 2u * wi;
+    const int32_t lo = (int32_t)(w & 0xFFFFu) - 32768, hi = (int32_t)(w >> 16) - 32768;
+    if (lo) atomicAdd(p, (unsigned long long)(long long)lo);
+    if (hi) atomicAdd(p + 1, (unsigned long long)(long long)hi);
   }
-  if constexpr (PRIME == kPrime61) bad |= any_hi >> 28;
-  const bool any_esc = __any(any_e);
-  if (PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0))
-    rows_tile<PRIME, MODE, K, NP, true, true>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
-  else
-    rows_tile<PRIME, MODE, K, NP, false, true>(args, r0, words, x0, x1, wf, wv, esc, any_esc);
-  return bad;
 }
 
 // The wave tiles are cut into `xcds` contiguous ranges, one per XCD, and every
@@ -540,6 +587,7 @@ template <int PRIME, int MODE, int K, typename KeyT, typename WT>
 __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> args) {
   // static, so that LDS addresses need no base: one block per CU holds it all
   __shared__ __align__(16) uint32_t words[kRowLdsBytes / 4];
+
   constexpr int NP = MODE == kTwoPoly ? 2 : 1;
   const uint32_t G = args.groups;
   const uint32_t g = blockIdx.x % G;
@@ -553,6 +601,10 @@ __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> arg
   const uint32_t X = args.xcds, home = (xcc & 15u) % X;
   const uint64_t W = (args.n + 64 * kRowKpt - 1) / (64 * kRowKpt);  // wave tiles
   uint32_t bad = 0;
+  // a group of one row keeps that row's coefficients for the whole launch
+  const auto c1 = load_row_coeffs<K, NP>(args.coeffs + (size_t)r0 * NP * K);
+  const bool one = args.rpg == 1;
+  constexpr uint64_t kWt = 64 * kRowKpt;  // keys per wave tile
   for (uint32_t k = 0; k < X; ++k) {
     const uint32_t x = home + k < X ? home + k : home + k - X;
     const uint64_t lo = W * x / X, hi = W * (x + 1) / X;
@@ -567,22 +619,118 @@ __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> arg
       if (wt0 >= hi) break;
       if (lane == 0) next = atomicAdd(q, 1u);
       const uint64_t wt1 = wt0 + kRowChunk < hi ? wt0 + kRowChunk : hi;
-      for (uint64_t wt = wt0; wt < wt1; ++wt)
-        bad |= rows_wave_tile<PRIME, MODE, K, NP>(args, r0, words, wt * (64 * kRowKpt), lane);
+      for (uint64_t wt = wt0; wt < wt1; ++wt) {
+        KeyT ka[kRowKpt];
+        WT wa[kRowKpt];
+        if ((wt + 1) * kWt <= args.n)
+          tile_issue<kRowKpt>(args.keys + wt * kWt + lane, args.weights + wt * kWt + lane, ka, wa);
+        __builtin_amdgcn_sched_barrier(0);
+        bad |= rows_wave_tile<PRIME, MODE, K, NP, kRowKpt>(args, c1, one, r0, words, wt, ka, wa, lane);
+      }
     }
   }
   if (bad) atomicOr(args.flags, kFlagDomain);
   __syncthreads();
-  // add field - 2^15 of every non-zero field into the global counters; word i
-  // holds buckets 2i and 2i + 1 of its row, so a wave's adds are contiguous
-  const uint32_t lw = args.log2m - 1;
-  for (uint32_t i = threadIdx.x; i < nwords; i += kRowBlock) {
-    const uint32_t w = words[i];
-    const uint32_t r = i >> lw, wi = i & ((1u << lw) - 1u);
-    unsigned long long* const p = args.table + ((size_t)(r0 + r) << args.log2m) + 2u * wi;
-    const int32_t lo = (int32_t)(w & 0xFFFFu) - 32768, hi = (int32_t)(w >> 16) - 32768;
-    if (lo) atomicAdd(p, (unsigned long long)(long long)lo);
-    if (hi) atomicAdd(p + 1, (unsigned long long)(long long)hi);
+  rows_flush(args, r0, words, nwords);
+}
+
+// One wave tile (64 * KPT keys from `base`) added to every row of the sketch
+// with device-scope int64 atomics; returns domain-error bits.
+template <int PRIME, int MODE, int K, int NP, int KPT, typename KeyT, typename WT>
+__device__ __forceinline__ uint32_t direct_wave_tile(const RowArgs<KeyT, WT>& args, uint64_t base, uint32_t lane) {
+  uint32_t x0[KPT], x1[KPT];
+  int64_t wv[KPT];
+  bool ok[KPT];
+  load_tile<KPT>(args.keys, args.weights, base, 64, lane, args.n, x0, x1, wv, ok);
+  uint32_t any_hi = 0;
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) any_hi |= x1[j];
+  const uint32_t bad = PRIME == kPrime61 ? any_hi >> 28 : 0u;  // key >= 2^60 breaks p >= 2u - 1
+  const bool wide = PRIME == kPrime61 && sizeof(KeyT) == 8 && __any(any_hi != 0);
+  uint64_t wneg[KPT];
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) wneg[j] = (uint64_t)wv[j] ^ (uint64_t)(-wv[j]);
+  for (uint32_t r = 0; r < args.rows; ++r) {
+    const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
+    unsigned long long* const row = args.table + ((size_t)r << args.log2m);
+    if (wide) {
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) {
+        uint32_t bk, m;
+        bucket_mask<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m, bk, m);
+        if (ok[j]) atomicAdd(&row[bk], masked_signed(m, wv[j], wneg[j]));
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) {
+        uint32_t bk, m;
+        bucket_mask<PRIME, MODE, K, false, NP>(c, x0[j], x1[j], args.log2m, bk, m);
+        if (ok[j]) atomicAdd(&row[bk], masked_signed(m, wv[j], wneg[j]));
+      }
+    }
+  }
+  return bad;
+}
+
+// Batched row-resident update: a persistent grid of one 1024-thread block per
+// CU takes items from one queue (zero at launch), in the order the host
+// listed them (largest first).  A rows item is one row group of one sketch
+// over a range of its wave tiles: the block sets the group's 16-bit fields to
+// their bias, its waves split the range's tiles, and the block then adds the
+// fields into the sketch's counters, all as k_update_rows does.  A direct item
+// (rpg 0) adds each key of its range to every row of its sketch with
+// device-scope atomics (streams much shorter than the table).  The next
+// item's index is taken while the current one runs.
+template <int PRIME, int MODE, int K, typename KeyT, typename WT, int KPT>
+__global__ __launch_bounds__(kRowBlock) void k_batch_rows(const BatchSketch* __restrict__ sks,
+                                                          const BatchRowItem* __restrict__ items, uint32_t nitems,
+                                                          uint32_t* __restrict__ queue) {
+  // the fields; between items, words[0] passes the next item's index to the block
+  __shared__ __align__(16) uint32_t words[kRowLdsBytes / 4];
+  constexpr int NP = MODE == kTwoPoly ? 2 : 1;
+  constexpr uint64_t kWt = 64 * KPT;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (threadIdx.x == 0) words[0] = atomicAdd(queue, 1u);
+  __syncthreads();
+  uint32_t it = __builtin_amdgcn_readfirstlane(words[0]);
+  __syncthreads();  // read by all before the fields are set
+  while (it < nitems) {
+    uint32_t pre = 0;
+    if (threadIdx.x == 0) pre = atomicAdd(queue, 1u);
+    const BatchRowItem item = uniform_load(items + it);
+    const BatchSketch sk = uniform_load(sks + item.sketch);
+    const RowArgs<KeyT, WT> a{(const KeyT*)sk.keys, (const WT*)sk.weights, sk.n, sk.coeffs, sk.rows, sk.log2m,
+                              item.rpg, 0, 0, sk.table, sk.flags, nullptr, 0};
+    uint32_t bad = 0;
+    if (item.rpg) {
+      const uint32_t nwords = item.rpg << (sk.log2m - 1);
+      for (uint32_t i = threadIdx.x; i < nwords; i += kRowBlock) words[i] = 0x80008000u;
+      __syncthreads();
+      const auto c1 = load_row_coeffs<K, NP>(sk.coeffs + (size_t)item.r0 * NP * K);
+      const bool one = item.rpg == 1;
+      for (uint64_t wt = item.wt_begin + wave; wt < item.wt_end; wt += kRowBlock / 64) {
+        KeyT ka[KPT];
+        WT wa[KPT];
+        if ((wt + 1) * kWt <= a.n) tile_issue<KPT>(a.keys + wt * kWt + lane, a.weights + wt * kWt + lane, ka, wa);
+        __builtin_amdgcn_sched_barrier(0);
+        bad |= rows_wave_tile<PRIME, MODE, K, NP, KPT>(a, c1, one, item.r0, words, wt, ka, wa, lane);
+      }
+      __syncthreads();
+      rows_flush(a, item.r0, words, nwords);
+    } else {
+      for (uint64_t wt = item.wt_begin + wave; wt < item.wt_end; wt += kRowBlock / 64)
+        bad |= direct_wave_tile<PRIME, MODE, K, NP, KPT>(a, wt * kWt, lane);
+    }
+    if (bad) atomicOr(sk.flags, kFlagDomain);
+    // every wave is done with the item (the flush has read the fields) before
+    // the next index is written over them; all read it before the next item
+    // sets the fields
+    __syncthreads();
+    if (threadIdx.x == 0) words[0] = pre;
+    __syncthreads();
+    it = __builtin_amdgcn_readfirstlane(words[0]);
+    __syncthreads();
   }
 }
 
@@ -1225,6 +1373,20 @@ hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t st) {
     hipLaunchKernelGGL((k_batch_global<PRIME, MODE, K, KeyT, WT>), dim3(b.glb_blocks), dim3(kBlock), 0, st,
                        b.sketches, b.glb_item_list, b.glb_items);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (b.row_items) {
+    // the queue starts at zero on every launch (a kernel, not a memset, so
+    // that a captured graph replays it)
+    hipError_t e = launch_fill_zero((unsigned long long*)b.row_queue, 1, st);
+    if (e != hipSuccess) return e;
+    if (b.row_kpt == 4)
+      hipLaunchKernelGGL((k_batch_rows<PRIME, MODE, K, KeyT, WT, 4>), dim3(b.row_blocks), dim3(kRowBlock), 0, st,
+                         b.sketches, b.row_item_list, b.row_items, b.row_queue);
+    else
+      hipLaunchKernelGGL((k_batch_rows<PRIME, MODE, K, KeyT, WT, 8>), dim3(b.row_blocks), dim3(kRowBlock), 0, st,
+                         b.sketches, b.row_item_list, b.row_items, b.row_queue);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   for (uint32_t r = 0; r < b.rounds; ++r) {

@@ -232,6 +232,13 @@ struct BatchLdsItem {         // keys [begin, end) of sketch `sketch`
   uint32_t sketch, pad;
   uint64_t begin, end;
 };
+struct BatchRowItem {         // batched row-resident update (k_batch_rows)
+  uint32_t sketch;            // index into the sketch list
+  uint32_t r0;                // first row of the item's row group
+  uint32_t rpg;               // rows of the group; 0: every row, direct device atomics
+  uint32_t pad;
+  uint64_t wt_begin, wt_end;  // wave tiles [wt_begin, wt_end) of the sketch's stream
+};
 struct BatchSegment {         // keys of one two-pass sketch handled in a round
   const void* keys;           // first key of the segment
   const void* weights;
@@ -264,6 +271,10 @@ struct BatchLaunch {
   uint32_t lds_items, lds_blocks, lds_bytes;
   const BatchLdsItem* glb_item_list;  // items of sketches updated with direct atomics
   uint32_t glb_items, glb_blocks;
+  const BatchRowItem* row_item_list;  // row-resident and direct items, largest first
+  uint32_t row_items, row_blocks;
+  uint32_t* row_queue;                // the row items' queue counter (8 bytes, zeroed per launch)
+  int row_kpt;                        // keys per lane of a wave tile of the row items: 4 or 8
   const BatchRound* round_list;  // host array
   uint32_t rounds;
   uint32_t bin_blocks, bin_lds_bytes, bin_lds_per_wave;
