@@ -315,7 +315,7 @@ def run_batched(args):
     batch = M.Batch(members)
     stream = torch.cuda.current_stream()
     t_tune = time.perf_counter()
-    chosen = batch.autotune(stream)
+    chosen = batch.options() if args.no_autotune else batch.autotune(stream)
     t_tune = time.perf_counter() - t_tune
     _log(f"batched: autotuned in {t_tune:.1f} s -> lds_table_max {chosen.lds_table_max}, "
          f"chunk {chosen.lds_chunk_keys}, combine {chosen.combine}, direct {chosen.direct_fraction}, "
@@ -791,6 +791,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy 1 GiB device to device (reference dispatch for HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched: keep the default options instead of autotuning (for profiles)")
     ap.add_argument("--no-naive", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -136,7 +136,9 @@ cs_status cs_query(cs_sketch* s, const void* keys, cs_dtype key_type, uint64_t n
                    hipStream_t stream);
 
 /* Update paths.  AUTO picks LDS when the whole table (rows*buckets*8 bytes)
- * fits in 64 KiB; else ROWS when a row has at most 2^16 buckets (each block
+ * fits in 64 KiB; else GLOBAL when the call has fewer than buckets/8 keys
+ * (fewer adds than a per-block copy of the table would clear and flush); else
+ * ROWS when a row has at most 2^16 buckets (each block
  * holds the rows of one row group in LDS as 16-bit fields, whose rare wraps
  * are carried into the int64 table exactly); else BINNED (two passes through
  * a library-owned workspace); else GLOBAL (one device-scope atomic per key and

@@ -30,7 +30,8 @@ typedef struct {
  *     (default 1/8; negative: never), where fewer updates reach the table
  *     than clearing and flushing a per-block copy would touch,
  *   - in LDS with int64 counters when rows*buckets*8 <= lds_table_max
- *     (default 65536, at most 163840; 8 puts no table there),
+ *     (default 8, which puts no table there, or 65536 when row_resident is
+ *     negative; at most 163840),
  *   - else row-resident when a row of 16-bit fields fits a block's LDS
  *     (buckets <= 2^16; the single-sketch row-resident update, one row group
  *     of one sketch per work item), unless row_resident is negative,

@@ -65,11 +65,14 @@ cs_status mcs::batch_plan(const cs_batch_item* items, size_t count, int kb, int 
                           const BatchPlanLimits& lim, BatchPlan* out) {
   BatchPlan& P = *out;
   P = BatchPlan{};
-  const uint32_t lds_max = opts.lds_table_max ? std::min(opts.lds_table_max, kMaxLdsTable) : kDefaultLdsMax;
+  const bool rows_on = opts.row_resident >= 0;
+  // with the row-resident class on, no table goes to the LDS class unless asked
+  const uint32_t lds_max = opts.lds_table_max ? std::min(opts.lds_table_max, kMaxLdsTable)
+                           : rows_on          ? 8u
+                                              : kDefaultLdsMax;
   const uint64_t chunk = opts.lds_chunk_keys ? opts.lds_chunk_keys : kDefaultChunk;
   P.combine = opts.combine >= 0;
   const double direct = opts.direct_fraction == 0.0 ? kDefaultDirect : opts.direct_fraction;
-  const bool rows_on = opts.row_resident >= 0;
   if (opts.keys_per_thread != 0 && opts.keys_per_thread != 4 && opts.keys_per_thread != 8)
     return fail(CS_EINVAL, "keys_per_thread must be 0, 4 or 8");
   P.row_kpt = opts.keys_per_thread ? (int)opts.keys_per_thread : 8;
@@ -177,8 +180,11 @@ cs_status mcs::batch_plan(const cs_batch_item* items, size_t count, int kb, int 
       const uint32_t per = r.rpg ? r.rpg : r.rows;     // rows an item adds a key to
       const uint64_t groups = r.rpg ? r.rows / r.rpg : 1;
       const uint64_t per_tile = wt_keys * per * (r.rpg ? 1 : 2);  // direct atomics cost about twice a field add
-      const uint64_t pieces = std::max<uint64_t>(1, std::min<uint64_t>((tiles + 15) / 16,
-                                                                         (tiles * per_tile + target - 1) / target));
+      // at most one piece per 16 wave tiles (a tile per wave) and, for a rows
+      // item, per 2m keys (its flush then costs at most about half its adds)
+      const uint64_t most = std::min<uint64_t>((tiles + 15) / 16, r.rpg ? r.n / (2ull << r.log2m) : ~0ull);
+      const uint64_t pieces =
+          std::max<uint64_t>(1, std::min<uint64_t>(most, (tiles * per_tile + target - 1) / target));
       const uint64_t fields = r.rpg ? ((uint64_t)r.rpg << r.log2m) / 4 : 0;  // clearing and flushing the fields
       for (uint64_t g = 0; g < groups; ++g)
         for (uint64_t pc = 0; pc < pieces; ++pc) {

@@ -339,8 +339,9 @@ UpdatePlan mcs::plan_update(const cs_sketch* s, uint64_t n) {
   const uint32_t rpg = rows_per_group(s->rows, s->log2m);
   int path = s->path;
   if (path == 0)
-    path = cells * 8 <= kLdsTableMax ? CS_PATH_LDS
-           : rpg                     ? CS_PATH_ROWS
+    path = cells * 8 <= kLdsTableMax         ? CS_PATH_LDS
+           : n * 8 < (1ull << s->log2m)      ? CS_PATH_GLOBAL
+           : rpg                             ? CS_PATH_ROWS
            : binned_fits(s, &log2g, &log2r) ? CS_PATH_BINNED
                                             : CS_PATH_GLOBAL;
   if (path == CS_PATH_LDS && cells * 8 > kLdsTableMax) path = CS_PATH_GLOBAL;
@@ -353,7 +354,12 @@ UpdatePlan mcs::plan_update(const cs_sketch* s, uint64_t n) {
     const uint64_t groups = s->rows / rpg;
     const uint64_t rtiles = (n + kRowTile - 1) / kRowTile;
     p.tiles = (uint32_t)std::min<uint64_t>(rtiles, 0xffffffffull);
-    p.blocks = (uint32_t)std::max<uint64_t>(groups, std::min<uint64_t>((uint64_t)dev.cus, groups * rtiles));
+    // Every block clears and flushes its group's fields, and the blocks of a
+    // group flush into the same counters at about the same time; a block
+    // therefore gets at least 2m keys (its flush then costs at most about half
+    // its adds), up to one block per CU.
+    const uint64_t per_group = std::max<uint64_t>(1, std::min<uint64_t>(rtiles, n / (2ull << s->log2m)));
+    p.blocks = (uint32_t)std::max<uint64_t>(groups, std::min<uint64_t>((uint64_t)dev.cus, groups * per_group));
     p.queues = s->d_queues;
   } else if (path == CS_PATH_LDS) {
     p.variant = kVariantLds;

@@ -46,17 +46,18 @@ def _oracle(spec, k, w, times=1):
     return t * times
 
 
-@pytest.mark.parametrize("row_resident", [1, -1])
-def test_batch_all_classes_and_graph_replays(row_resident):
+@pytest.mark.parametrize("row_resident,lds_table_max,classes", [
+    (0, 0, (3, 0, 7, 1)),        # default: one persistent launch for every table of up to 2^16 buckets
+    (1, 65536, (3, 2, 5, 1)),    # small tables in the LDS class beside it
+    (-1, 0, (3, 2, 0, 6)),       # no row-resident class: LDS and two-pass classes
+])
+def test_batch_all_classes_and_graph_replays(row_resident, lds_table_max, classes):
     members, specs = _members()
     opts = M.BatchOptions()
     opts.row_resident = row_resident
+    opts.lds_table_max = lds_table_max
     b = M.Batch([(sk, k, w) for sk, k, w in members], opts)
-    ng, nl, nr, nt = b.classes()
-    if row_resident > 0:
-        assert ng >= 2 and nl >= 2 and nr >= 5 and nt == 1, (ng, nl, nr, nt)
-    else:
-        assert ng >= 2 and nl >= 2 and nr == 0 and nt >= 3, (ng, nl, nr, nt)
+    assert b.classes() == classes
     want = [_oracle(sp, k, w) for sp, (sk, k, w) in zip(specs, members)]
     for replay in range(1, 4):
         b.update()
