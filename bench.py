@@ -114,9 +114,100 @@ def measured_traffic(workload: str, n: int):
     except (OSError, ValueError):
         return None
     entry = t.get("workloads", {}).get(workload)
-    if entry is None or entry.get("n") != n or t.get("sources_sha256") != kernel_sources_sha256():
+    if entry is None or entry.get("n") != n or entry.get("sources_sha256") != kernel_sources_sha256():
         return None
     return entry.get("hbm_bytes_per_launch")
+
+
+# Library kernels that are not part of the measured launch (the step's reset and estimate).
+TRAFFIC_EXCLUDE = ("k_estimate", "k_fill_zero")
+
+
+def summarize_traffic(args):
+    """Turns the two counter runs of a workload (FETCH_SIZE, then WRITE_SIZE, each with
+    --calib-copy) into HBM bytes per launch of its library kernels, calibrated on the 1 GiB
+    copy, and records them with the hash of the kernel sources in profiles/hbm_traffic.json
+    and profiles/hbm_traffic.md.  The runs are `bench.py --workload W --steps S --warmup U
+    --no-cpu-baseline --no-naive --calib-copy` under rocprofv3 --pmc; pass the same W, S, U."""
+    import csv
+    import glob
+
+    def per_dispatch(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            sys.exit(f"bench.py: no counter_collection.csv under {d}")
+        out = {}
+        for f in files:
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] != counter:
+                        continue
+                    e = out.setdefault((f, int(r["Dispatch_Id"])), [r["Kernel_Name"], 0.0])
+                    e[1] += float(r["Counter_Value"])
+        return list(out.values())
+
+    launches = args.steps + args.warmup
+    res = {}
+    for counter, d in (("FETCH_SIZE", args.traffic_summary[0]), ("WRITE_SIZE", args.traffic_summary[1])):
+        rows = per_dispatch(d, counter)
+        copies = [v for name, v in rows if "copyBuffer" in name]
+        if not copies:
+            sys.exit(f"bench.py: no copy dispatch in the {counter} run (was it made with --calib-copy?)")
+        factor = (1 << 30) / (max(copies) * 1024.0)
+        mine = [(name, v) for name, v in rows if "mcs::" in name and not any(x in name for x in TRAFFIC_EXCLUDE)]
+        kernels = sorted({name.split("<")[0].split("(")[0].replace("void ", "") for name, _ in mine})
+        res[counter] = (factor, sum(v for _, v in mine) * 1024.0 * factor / launches, kernels)
+    wl = args.workload
+    if wl in SKETCH_WORKLOADS:
+        w = SKETCH_WORKLOADS[wl]
+        n = args.n or w["n"]
+        algo = n * (w["kbytes"] + w["wbytes"])  # keys and weights, read once
+    else:
+        w = DIVMOD_WORKLOADS[wl]
+        n = args.n or w["n"]
+        algo = n * 8 * (w["limbs"] + w["qlimbs"] + w["limbs"] - 1)  # x in; quotient and remainder out
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        t = {}
+    t.pop("sources_sha256", None)
+    t.setdefault("workloads", {})[wl] = {
+        "launch": " + ".join(res["FETCH_SIZE"][2]), "n": n,
+        "fetch_bytes_per_launch": int(res["FETCH_SIZE"][1]), "write_bytes_per_launch": int(res["WRITE_SIZE"][1]),
+        "hbm_bytes_per_launch": int(res["FETCH_SIZE"][1] + res["WRITE_SIZE"][1]),
+        "algorithmic_bytes_per_launch": algo,
+        "ratio": round((res["FETCH_SIZE"][1] + res["WRITE_SIZE"][1]) / algo, 3),
+        "fetch_factor": round(res["FETCH_SIZE"][0], 5), "write_factor": round(res["WRITE_SIZE"][0], 5),
+        "sources_sha256": kernel_sources_sha256()}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(t, fh, indent=1)
+    lines = ["# HBM traffic per launch — FETCH_SIZE and WRITE_SIZE, copy-calibrated", "",
+             "Each counter in a run of its own (from the repository root, one MI355X), then the summary:", "",
+             "```",
+             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d /tmp/pmc_<workload>_FETCH_SIZE -o run -- \\",
+             "    python3 bench.py --workload <workload> --steps 2 --warmup 1 --no-cpu-baseline --no-naive --calib-copy",
+             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d /tmp/pmc_<workload>_WRITE_SIZE -o run -- \\",
+             "    python3 bench.py --workload <workload> --steps 2 --warmup 1 --no-cpu-baseline --no-naive --calib-copy",
+             "python3 bench.py --workload <workload> --steps 2 --warmup 1 \\",
+             "    --traffic-summary /tmp/pmc_<workload>_FETCH_SIZE /tmp/pmc_<workload>_WRITE_SIZE",
+             "```", "",
+             "`--calib-copy` first copies 1 GiB device to device (`__amd_rocclr_copyBuffer`, 2^30 bytes read",
+             "and 2^30 written); each factor is known bytes / (counter KiB x 1024) of that dispatch. The bytes",
+             "are those of the library's kernels in the run (not the step's reset and estimate) per launch.",
+             "A row stands for the kernel sources it was taken on (sha256 over the kernel sources, as",
+             "bench.py computes it); bench.py reports `traffic` only while that hash matches.", "",
+             "| Workload | Kernels | Fetch bytes | Write bytes | HBM bytes | Algorithmic bytes | HBM / algorithmic "
+             "| Factors (fetch, write) | Sources sha256 |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    for name, e in t["workloads"].items():
+        lines.append(f"| {name} | {e['launch']} | {e['fetch_bytes_per_launch']:.4g} | {e['write_bytes_per_launch']:.4g} "
+                     f"| {e['hbm_bytes_per_launch']:.4g} | {e['algorithmic_bytes_per_launch']:.4g} | {e['ratio']} "
+                     f"| {e.get('fetch_factor', '-')}, {e.get('write_factor', '-')} "
+                     f"| `{e.get('sources_sha256', 'earlier sources')[:16]}` |")
+    with open(os.path.join(HERE, "profiles", "hbm_traffic.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return t["workloads"][wl]
 
 
 def update_kernels(sk, n, path=0) -> str:
@@ -794,7 +885,13 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched: keep the default options instead of autotuning (for profiles)")
     ap.add_argument("--no-naive", action="store_true")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="summarize the FETCH_SIZE and WRITE_SIZE counter runs of --workload into "
+                         "profiles/hbm_traffic.json (no GPU work)")
     args = ap.parse_args()
+    if args.traffic_summary:
+        print(json.dumps(summarize_traffic(args)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; the benchmark runs on one GPU "
               f"(the sketch would shard by key range plus one int64 all-reduce, which is not implemented)",

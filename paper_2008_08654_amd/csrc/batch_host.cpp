@@ -189,8 +189,9 @@ cs_status mcs::batch_plan(const cs_batch_item* items, size_t count, int kb, int 
       for (uint64_t g = 0; g < groups; ++g)
         for (uint64_t pc = 0; pc < pieces; ++pc) {
           const uint64_t b = tiles * pc / pieces, e = tiles * (pc + 1) / pieces;
+          const uint32_t spread = (uint32_t)(pc & 0xFFFF) | (uint32_t)std::min<uint64_t>(pieces, 0xFFFF) << 16;
           all.push_back(Costed{(e - b) * per_tile + fields,
-                               BatchRowItem{r.id, (uint32_t)(g * r.rpg), r.rpg, 0, b, e}});
+                               BatchRowItem{r.id, (uint32_t)(g * r.rpg), r.rpg, spread, b, e}});
         }
     }
     std::stable_sort(all.begin(), all.end(), [](const Costed& a, const Costed& b) { return a.cost > b.cost; });

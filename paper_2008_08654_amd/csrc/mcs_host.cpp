@@ -160,7 +160,7 @@ static uint32_t est_slices_for(uint32_t log2m) {
 
 size_t mcs::sketch_device_bytes(uint32_t rows, uint32_t log2m, cs_mode mode, uint32_t k) {
   const size_t ncoef = (size_t)rows * npoly(mode) * k;
-  return ((size_t)rows << log2m) * 8 + ncoef * sizeof(uint4) + 64 + sizeof(uint32_t) * kRowXcds * kMaxRows +
+  return ((size_t)rows << log2m) * 8 + ncoef * sizeof(uint4) + 64 + sizeof(uint32_t) * kRowRanges * kMaxRows +
          sizeof(EstPartial) * rows * est_slices_for(log2m) + sizeof(int64_t) * (rows + 2);
 }
 
@@ -197,7 +197,7 @@ static cs_status create_common(uint32_t rows, uint64_t buckets, cs_prime prime, 
   if ((e = hipMalloc(&s->d_table, cells * 8)) != hipSuccess ||
       (e = hipMalloc(&s->d_coeffs, ncoef * sizeof(uint4))) != hipSuccess ||
       (e = hipMalloc(&s->d_flags, 64)) != hipSuccess ||
-      (e = hipMalloc(&s->d_queues, sizeof(uint32_t) * kRowXcds * kMaxRows)) != hipSuccess) {
+      (e = hipMalloc(&s->d_queues, sizeof(uint32_t) * kRowRanges * kMaxRows)) != hipSuccess) {
     cs_destroy(s);
     return fail(CS_ENOMEM, "device allocation of %zu counters: %s", cells, hipGetErrorString(e));
   }
@@ -360,6 +360,14 @@ UpdatePlan mcs::plan_update(const cs_sketch* s, uint64_t n) {
     // its adds), up to one block per CU.
     const uint64_t per_group = std::max<uint64_t>(1, std::min<uint64_t>(rtiles, n / (2ull << s->log2m)));
     p.blocks = (uint32_t)std::max<uint64_t>(groups, std::min<uint64_t>((uint64_t)dev.cus, groups * per_group));
+    // With at least one block per group on every XCD, the same number of
+    // blocks per group on each XCD's range and the rest on the pool range
+    // (k_update_rows); the grid is then a multiple of the XCD count.
+    p.range_blocks = 0;
+    if (p.blocks >= groups * kRowXcds && groups <= kMaxRows) {
+      p.blocks -= p.blocks % kRowXcds;
+      p.range_blocks = (uint32_t)(p.blocks / kRowXcds / groups * groups);
+    }
     p.queues = s->d_queues;
   } else if (path == CS_PATH_LDS) {
     p.variant = kVariantLds;

@@ -21,7 +21,7 @@ struct cs_sketch {
   int64_t* d_table = nullptr;      // rows x 2^log2m, row-major
   uint64_t* d_coeffs = nullptr;    // uint4 records, [row][poly][i]
   uint32_t* d_flags = nullptr;     // sticky flags (kFlagDomain | kFlagOverflow)
-  uint32_t* d_queues = nullptr;    // work queues of the row-resident update (kRowXcds * kMaxRows)
+  uint32_t* d_queues = nullptr;    // work queues of the row-resident update (kRowRanges * kMaxRows)
   void* d_est_part = nullptr;      // EstPartial[rows * est_slices]
   int64_t* d_est_out = nullptr;    // median, rows values, flags
   int64_t* h_est_out = nullptr;    // pinned copy of d_est_out

@@ -561,12 +561,17 @@ __device__ __forceinline__ uint32_t rows_wave_tile(const RowArgs<KeyT, WT>& args
 
 // Adds field - 2^15 of every non-zero field of the block's group (rpg rows
 // from row r0, nwords LDS words) into the global counters; word i holds
-// buckets 2i and 2i + 1 of its row, so a wave's adds are contiguous.
+// buckets 2i and 2i + 1 of its row, so a wave's adds are contiguous.  Blocks
+// of one group flush at about the same time into the same counters; block
+// `rank` of `ranks` starts its pass at its own fraction of the words, so that
+// their atomics meet different counters instead of queueing on the same ones.
 template <typename KeyT, typename WT>
 __device__ __forceinline__ void rows_flush(const RowArgs<KeyT, WT>& args, uint32_t r0, const uint32_t* words,
-                                           uint32_t nwords) {
+                                           uint32_t nwords, uint32_t rank, uint32_t ranks) {
   const uint32_t lw = args.log2m - 1;
-  for (uint32_t i = threadIdx.x; i < nwords; i += kRowBlock) {
+  const uint32_t start = (uint32_t)(((uint64_t)nwords * (rank % ranks) / ranks) & ~63ull);
+  for (uint32_t k = threadIdx.x; k < nwords; k += kRowBlock) {
+    const uint32_t i = k + start < nwords ? k + start : k + start - nwords;
     const uint32_t w = words[i];
     const uint32_t r = i >> lw, wi = i & ((1u << lw) - 1u);
     unsigned long long* const p = args.table + ((size_t)(r0 + r) << args.log2m) + 2u * wi;
@@ -576,13 +581,23 @@ __device__ __forceinline__ void rows_flush(const RowArgs<KeyT, WT>& args, uint32
   }
 }
 
-// The wave tiles are cut into `xcds` contiguous ranges, one per XCD, and every
-// (range, row group) pair has a queue: a counter of taken chunks of kRowChunk
-// wave tiles.  A wave takes chunks for its block's group from its own XCD's
-// range first, so the nine (or however many) groups read each tile through
-// the same L2, then from the other ranges in turn until all are empty.  Every
+// The wave tiles are cut into contiguous ranges, one per XCD plus a pool, and
+// every (range, row group) pair has a queue: a counter of taken chunks of
+// kRowChunk wave tiles.  A wave takes chunks for its block's group from its
+// home range first, then from the others in turn until all are empty; every
 // wave tile of every group is taken exactly once (the counters are zero at
-// launch).  No wave waits for another.
+// launch) and no wave waits for another.
+//
+// The groups read each tile through the L2 of the XCD whose range holds it,
+// and a tile stays there only while the groups pass it at about the same
+// time, so every XCD gets the same number of blocks per group: with
+// range_blocks > 0, block b counts as block b / xcds of XCD b mod xcds (the
+// hardware's round-robin placement), the first range_blocks of each XCD
+// take group j mod groups and the XCD's range (the XCD they actually run on,
+// read from the hardware), and the rest take groups in turn and the pool,
+// which holds the pool blocks' share of the tiles.  Without it (few blocks)
+// block b takes group b mod groups and there is no pool.  Either way every
+// group has a block, so every queue is drained.
 template <int PRIME, int MODE, int K, typename KeyT, typename WT>
 __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> args) {
   // static, so that LDS addresses need no base: one block per CU holds it all
@@ -590,25 +605,44 @@ __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> arg
 
   constexpr int NP = MODE == kTwoPoly ? 2 : 1;
   const uint32_t G = args.groups;
-  const uint32_t g = blockIdx.x % G;
+  const uint32_t X = args.xcds;
+  uint32_t xcc;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+  const uint32_t RB = args.range_blocks;
+  const uint32_t per_xcd = gridDim.x / X, j = blockIdx.x / X;
+  const bool pool_block = RB && j >= RB;
+  const uint32_t g = !RB ? blockIdx.x % G
+                     : j < RB ? j % G
+                              : ((blockIdx.x % X) * (per_xcd - RB) + (j - RB)) % G;
+  const uint32_t NR = RB && per_xcd > RB ? X + 1 : X;  // ranges: the XCDs' and the pool
+  const uint32_t home = pool_block ? X : (xcc & 15u) % X;
   const uint32_t r0 = g * args.rpg;
   const uint32_t nwords = args.rpg << (args.log2m - 1);
   for (uint32_t i = threadIdx.x; i < nwords; i += kRowBlock) words[i] = 0x80008000u;
   __syncthreads();
   const uint32_t lane = threadIdx.x & 63;
-  uint32_t xcc;
-  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
-  const uint32_t X = args.xcds, home = (xcc & 15u) % X;
   const uint64_t W = (args.n + 64 * kRowKpt - 1) / (64 * kRowKpt);  // wave tiles
+  // the XCD ranges end where the pool begins: the pool blocks' share of the tiles
+  const uint64_t Wx = NR > X ? W * RB / per_xcd : W;
   uint32_t bad = 0;
   // a group of one row keeps that row's coefficients for the whole launch
   const auto c1 = load_row_coeffs<K, NP>(args.coeffs + (size_t)r0 * NP * K);
   const bool one = args.rpg == 1;
   constexpr uint64_t kWt = 64 * kRowKpt;  // keys per wave tile
-  for (uint32_t k = 0; k < X; ++k) {
-    const uint32_t x = home + k < X ? home + k : home + k - X;
-    const uint64_t lo = W * x / X, hi = W * (x + 1) / X;
+  for (uint32_t k = 0; k < NR; ++k) {
+    const uint32_t x = home + k < NR ? home + k : home + k - NR;
+    const uint64_t lo = x < X ? Wx * x / X : Wx, hi = x < X ? Wx * (x + 1) / X : W;
     uint32_t* const q = args.queues + x * G + g;
+    if (k > 0) {
+      // Another XCD's range: most are drained by the time a wave gets here.
+      // A counter only grows during the launch, so a plain read that already
+      // shows the range drained needs no atomic (the atomics of one counter
+      // are served one after another; thousands of waves probing every range
+      // with them cost more than the hashing of a small update).
+      uint32_t seen = 0;
+      if (lane == 0) seen = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lo + (uint64_t)__builtin_amdgcn_readfirstlane(seen) * kRowChunk >= hi) continue;
+    }
     // the next chunk is taken before the current one is processed, so the
     // atomic's round trip overlaps the hashing
     uint32_t next = 0;
@@ -631,7 +665,7 @@ __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> arg
   }
   if (bad) atomicOr(args.flags, kFlagDomain);
   __syncthreads();
-  rows_flush(args, r0, words, nwords);
+  rows_flush(args, r0, words, nwords, blockIdx.x / G, gridDim.x / G);
 }
 
 // One wave tile (64 * KPT keys from `base`) added to every row of the sketch
@@ -701,7 +735,7 @@ __global__ __launch_bounds__(kRowBlock) void k_batch_rows(const BatchSketch* __r
     const BatchRowItem item = uniform_load(items + it);
     const BatchSketch sk = uniform_load(sks + item.sketch);
     const RowArgs<KeyT, WT> a{(const KeyT*)sk.keys, (const WT*)sk.weights, sk.n, sk.coeffs, sk.rows, sk.log2m,
-                              item.rpg, 0, 0, sk.table, sk.flags, nullptr, 0};
+                              item.rpg, 0, 0, sk.table, sk.flags, nullptr, 0, 0};
     uint32_t bad = 0;
     if (item.rpg) {
       const uint32_t nwords = item.rpg << (sk.log2m - 1);
@@ -717,7 +751,7 @@ __global__ __launch_bounds__(kRowBlock) void k_batch_rows(const BatchSketch* __r
         bad |= rows_wave_tile<PRIME, MODE, K, NP, KPT>(a, c1, one, item.r0, words, wt, ka, wa, lane);
       }
       __syncthreads();
-      rows_flush(a, item.r0, words, nwords);
+      rows_flush(a, item.r0, words, nwords, item.spread & 0xFFFFu, item.spread >> 16);
     } else {
       for (uint64_t wt = item.wt_begin + wave; wt < item.wt_end; wt += kRowBlock / 64)
         bad |= direct_wave_tile<PRIME, MODE, K, NP, KPT>(a, wt * kWt, lane);
@@ -1474,9 +1508,9 @@ hipError_t launch_update_t(const UpdatePlan& plan, const UpdateArgs<KeyT, WT>& a
   }
   if (plan.variant == kVariantRows) {
     RowArgs<KeyT, WT> r{a.keys, a.weights, a.n, a.coeffs, a.rows, a.log2m, plan.rpg, a.rows / plan.rpg,
-                        plan.tiles, a.table, a.flags, plan.queues, kRowXcds};
+                        plan.tiles, a.table, a.flags, plan.queues, kRowXcds, plan.range_blocks};
     // the queues start at zero (a fill kernel: no memset node in a captured graph)
-    hipError_t ez = launch_fill_zero((unsigned long long*)plan.queues, kRowXcds * kMaxRows / 2, st);
+    hipError_t ez = launch_fill_zero((unsigned long long*)plan.queues, kRowRanges * kMaxRows / 2, st);
     if (ez != hipSuccess) return ez;
     hipLaunchKernelGGL((k_update_rows<PRIME, MODE, K, KeyT, WT>), dim3(plan.blocks), dim3(kRowBlock), 0, st, r);
     return hipGetLastError();

@@ -39,8 +39,9 @@ constexpr int kRowKpt = 8;                          // keys per thread per tile
 constexpr uint32_t kRowTile = kRowBlock * kRowKpt;  // keys per tile
 constexpr uint32_t kRowMaxLog2m = 16;               // a row of 16-bit fields fits LDS
 constexpr uint32_t kRowLdsBytes = 160 * 1024;       // LDS a block may hold
-constexpr uint32_t kRowChunk = 8;                   // wave tiles a wave takes from a queue at once
+constexpr uint32_t kRowChunk = 32;                  // wave tiles a wave takes from a queue at once
 constexpr uint32_t kRowXcds = 8;                    // XCDs of the GPU: key ranges and queues per row group
+constexpr uint32_t kRowRanges = kRowXcds + 1;       // the XCDs' key ranges and one pool range
 
 // two-pass (binned) update
 constexpr int kBinKpt = 8;                          // keys per thread in a pass-1 tile
@@ -72,7 +73,8 @@ struct UpdatePlan {
   uint32_t* desc;       // [tiles][rows][G + 1]
   // row-resident variant
   uint32_t rpg;         // rows per row group (a divisor of rows)
-  uint32_t* queues;     // kRowXcds * kMaxRows work-queue counters (the sketch's)
+  uint32_t range_blocks;  // per XCD, blocks that work on the XCD's range (a multiple of the groups; 0: all)
+  uint32_t* queues;     // kRowRanges * kMaxRows work-queue counters (the sketch's)
 };
 
 // Row-resident update: block b holds the 16-bit fields of row group b mod
@@ -91,8 +93,9 @@ struct RowArgs {
   uint32_t tiles;
   unsigned long long* table;
   uint32_t* flags;
-  uint32_t* queues;  // xcds * groups counters, zero at launch
+  uint32_t* queues;  // (xcds + 1) * groups counters, zero at launch
   uint32_t xcds;
+  uint32_t range_blocks;  // see k_update_rows (0 in the batched kernel)
 };
 
 template <typename KeyT, typename WT>
@@ -236,7 +239,7 @@ struct BatchRowItem {         // batched row-resident update (k_batch_rows)
   uint32_t sketch;            // index into the sketch list
   uint32_t r0;                // first row of the item's row group
   uint32_t rpg;               // rows of the group; 0: every row, direct device atomics
-  uint32_t pad;
+  uint32_t spread;            // piece index | pieces << 16 (16 bits each): staggers the pieces' flushes
   uint64_t wt_begin, wt_end;  // wave tiles [wt_begin, wt_end) of the sketch's stream
 };
 struct BatchSegment {         // keys of one two-pass sketch handled in a round
