@@ -867,6 +867,35 @@ def run_divmod(args, wl):
     return out
 
 
+def summarize_kernel_stats(args):
+    """Writes profiles/<name>.md from a `rocprofv3 --kernel-trace --stats --output-format csv` run:
+    the kernels by total time, with the command that made the run."""
+    import csv
+    import glob
+    d, name = args.profile_summary
+    files = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        sys.exit(f"bench.py: no kernel_stats.csv under {d}")
+    with open(files[0]) as fh:
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel statistics — {args.profile_title or name}", "",
+             "Command (from the repository root, one MI355X):", "", "```",
+             f"rocprofv3 --kernel-trace --stats --output-format csv -d /tmp/{name} -o run -- \\",
+             f"    python3 {args.profile_command}", "```", "",
+             "The input generators' torch kernels run too (bench.py does not time them). Durations in "
+             "microseconds.", "",
+             "| Kernel | Calls | Avg us | Min us | Max us | % of GPU time |", "|---|---|---|---|---|---|"]
+    for r in rows[:14]:
+        kname = r["Name"] if len(r["Name"]) <= 110 else r["Name"][:107] + "..."
+        lines.append(f"| `{kname}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    out = os.path.join(HERE, "profiles", name + ".md")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return {"written": out, "kernels": len(rows)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -888,7 +917,14 @@ def main():
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="summarize the FETCH_SIZE and WRITE_SIZE counter runs of --workload into "
                          "profiles/hbm_traffic.json (no GPU work)")
+    ap.add_argument("--profile-summary", nargs=2, metavar=("DIR", "NAME"), default=None,
+                    help="write profiles/NAME.md from the rocprofv3 kernel statistics under DIR (no GPU work)")
+    ap.add_argument("--profile-title", default=None)
+    ap.add_argument("--profile-command", default="bench.py", help="the profiled command, for the summary")
     args = ap.parse_args()
+    if args.profile_summary:
+        print(json.dumps(summarize_kernel_stats(args)), flush=True)
+        return
     if args.traffic_summary:
         print(json.dumps(summarize_traffic(args)), flush=True)
         return
