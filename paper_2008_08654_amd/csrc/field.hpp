@@ -44,6 +44,10 @@ __device__ __forceinline__ F61 p61_step_x32(F61 y, uint32_t x, F61 a) {
   uint64_t u = mad64(y.w1, x, (uint64_t)hi32(t) + a.w1);   // bits 32..95
   // P = u * 2^32 + lo32(t);  P & p = (u & (2^29-1)) * 2^32 + lo32(t);  P >> 61 = u >> 29
   uint64_t low = ((uint64_t)(lo32(u) & kMask29) << 32) | lo32(t);
+  // keep low as one register pair: the low word is already in t's pair, so
+  // forming it costs only the mask; without this the adds get reassociated
+  // around extra moves when two keys' steps are interleaved
+  asm volatile("" : "+v"(low));
   uint64_t r = low + (u >> 29);
   return F61{lo32(r), hi32(r)};
 }

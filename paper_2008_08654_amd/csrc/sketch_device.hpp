@@ -62,6 +62,21 @@ __device__ __forceinline__ F61 horner61_x32(const RowCoeffs<K, NP>& c, int q, ui
   return y;
 }
 
+// The same for two keys, their steps interleaved: the two chains are
+// independent, so each fills the other's dependency stalls.
+template <int K, int NP>
+__device__ __forceinline__ void horner61_x32_pair(const RowCoeffs<K, NP>& c, int q, uint32_t xa, uint32_t xb, F61& ya,
+                                                  F61& yb) {
+  ya = F61{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
+  yb = ya;
+#pragma unroll
+  for (int i = K - 2; i >= 0; --i) {
+    const F61 a{c.w[q * K + i][0], c.w[q * K + i][1]};
+    ya = p61_step_x32(ya, xa, a);
+    yb = p61_step_x32(yb, xb, a);
+  }
+}
+
 template <int K, int NP>
 __device__ __forceinline__ F61 horner61_x64(const RowCoeffs<K, NP>& c, int q, uint32_t x0, uint32_t x1) {
   F61 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
@@ -427,7 +442,16 @@ __device__ __forceinline__ void row_update(const RowArgs<KeyT, WT>& args, const 
     asm volatile("v_mov_b32 %0, %1" : "=v"(rowoff) : "s"(r * 2u * m));
     uint32_t code[NK], old[NK], sh[NK];
     int32_t sw[NK];
-    {
+    if constexpr (PRIME == kPrime61 && MODE == kTwoForOne && !WIDE && NK % 2 == 0) {
+      // the low-bit split: the code is the low word of the reduced hash
+#pragma unroll
+      for (int j = 0; j < NK; j += 2) {
+        F61 ya, yb;
+        horner61_x32_pair<K, NP>(c, 0, x0[j], x0[j + 1], ya, yb);
+        code[j] = p61_final_lo(ya);
+        code[j + 1] = p61_final_lo(yb);
+      }
+    } else {
 #pragma unroll
       for (int j = 0; j < NK; ++j) code[j] = bucket_code<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m);
     }
