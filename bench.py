@@ -762,6 +762,10 @@ CEILING_PROBES = [  # (probe id, name, unit of one operation, iters, buffer byte
     (7, "global int64 atomics, random over 4.5 MiB", "atomics", 64, 9 << 19),
     (7, "global int64 atomics, random over 40 MiB", "atomics", 64, 40 << 20),
     (8, "global int64 atomics, coalesced over 4.5 MiB", "atomics", 512, 9 << 19),
+    (9, "v_mov_b32", "lane-instructions", 2000, 8),
+    (10, "v_bfe_u32", "lane-instructions", 2000, 8),
+    (11, "v_and_or_b32", "lane-instructions", 2000, 8),
+    (12, "v_xad_u32", "lane-instructions", 2000, 8),
 ]
 
 

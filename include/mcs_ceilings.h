@@ -24,7 +24,11 @@ typedef enum {
   CS_CEIL_LDS_ADD_U64 = 5,             /* ds_add_u64 at random addresses of a 64 KiB table */
   CS_CEIL_LDS_ADD_RTN_U32 = 6,         /* ds_add_rtn_u32 at random addresses of a 64 KiB table */
   CS_CEIL_GLOBAL_ATOMIC_RANDOM = 7,    /* device-scope int64 atomics at random counters */
-  CS_CEIL_GLOBAL_ATOMIC_COALESCED = 8  /* the same, a wave's lanes on consecutive counters */
+  CS_CEIL_GLOBAL_ATOMIC_COALESCED = 8, /* the same, a wave's lanes on consecutive counters */
+  CS_CEIL_MOV_B32 = 9,                 /* v_mov_b32 (register copy) */
+  CS_CEIL_BFE_U32 = 10,                /* v_bfe_u32 (a three-operand 32-bit instruction) */
+  CS_CEIL_AND_OR_B32 = 11,             /* v_and_or_b32 */
+  CS_CEIL_XAD_U32 = 12                 /* v_xad_u32 */
 } cs_ceiling;
 
 /* Enqueues one launch of probe `probe` on `stream` and writes to *ops (host)

@@ -39,8 +39,16 @@ __global__ __launch_bounds__(kCeilBlock) void k_issue(uint32_t iters, uint64_t* 
           asm volatile("v_mad_u64_u32 %0, vcc, %1, %2, %0" : "+v"(a[i]) : "v"(x), "v"(y) : "vcc");
         else if constexpr (OP == CS_CEIL_LSHL_ADD_U64)
           asm volatile("v_lshl_add_u64 %0, %0, 1, %1" : "+v"(a[i]) : "v"((uint64_t)y));
-        else
+        else if constexpr (OP == CS_CEIL_LSHRREV_B64)
           asm volatile("v_lshrrev_b64 %0, 1, %0" : "+v"(a[i]));
+        else if constexpr (OP == CS_CEIL_MOV_B32)
+          asm volatile("v_mov_b32 %0, %1" : "=v"(b[i]) : "v"(b[(i + 1) % kChains]));
+        else if constexpr (OP == CS_CEIL_BFE_U32)
+          asm volatile("v_bfe_u32 %0, %0, %1, 16" : "+v"(b[i]) : "v"(x));
+        else if constexpr (OP == CS_CEIL_AND_OR_B32)
+          asm volatile("v_and_or_b32 %0, %0, %1, %2" : "+v"(b[i]) : "v"(x), "v"(y));
+        else
+          asm volatile("v_xad_u32 %0, %0, %1, %2" : "+v"(b[i]) : "v"(x), "v"(y));
       }
     }
   }
@@ -124,7 +132,11 @@ extern "C" cs_status cs_ceiling_run(int probe, void* buffer, uint64_t bytes, uin
     case CS_CEIL_VALU_ADD32:
     case CS_CEIL_MAD_U64_U32:
     case CS_CEIL_LSHL_ADD_U64:
-    case CS_CEIL_LSHRREV_B64: {
+    case CS_CEIL_LSHRREV_B64:
+    case CS_CEIL_MOV_B32:
+    case CS_CEIL_BFE_U32:
+    case CS_CEIL_AND_OR_B32:
+    case CS_CEIL_XAD_U32: {
       if (iters == 0) return fail(CS_EINVAL, "iters must be positive");
       uint64_t* sink = (uint64_t*)buffer;
       if (!sink || bytes < 8) return fail(CS_EINVAL, "the issue probes need an 8-byte device buffer");
@@ -134,8 +146,16 @@ extern "C" cs_status cs_ceiling_run(int probe, void* buffer, uint64_t bytes, uin
         hipLaunchKernelGGL(k_issue<CS_CEIL_MAD_U64_U32>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
       else if (probe == CS_CEIL_LSHL_ADD_U64)
         hipLaunchKernelGGL(k_issue<CS_CEIL_LSHL_ADD_U64>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
-      else
+      else if (probe == CS_CEIL_LSHRREV_B64)
         hipLaunchKernelGGL(k_issue<CS_CEIL_LSHRREV_B64>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
+      else if (probe == CS_CEIL_MOV_B32)
+        hipLaunchKernelGGL(k_issue<CS_CEIL_MOV_B32>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
+      else if (probe == CS_CEIL_BFE_U32)
+        hipLaunchKernelGGL(k_issue<CS_CEIL_BFE_U32>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
+      else if (probe == CS_CEIL_AND_OR_B32)
+        hipLaunchKernelGGL(k_issue<CS_CEIL_AND_OR_B32>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
+      else
+        hipLaunchKernelGGL(k_issue<CS_CEIL_XAD_U32>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
       count = (uint64_t)grid * kCeilBlock * iters * kChains * kUnroll;  // lane-instructions
       break;
     }
