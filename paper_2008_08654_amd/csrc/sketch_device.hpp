@@ -584,24 +584,23 @@ __device__ __forceinline__ uint32_t rows_wave_tile(const RowArgs<KeyT, WT>& args
 }
 
 // Adds field - 2^15 of every non-zero field of the block's group (rpg rows
-// from row r0, nwords LDS words) into the global counters; word i holds
-// buckets 2i and 2i + 1 of its row, so a wave's adds are contiguous.  Blocks
-// of one group flush at about the same time into the same counters; block
-// `rank` of `ranks` starts its pass at its own fraction of the words, so that
-// their atomics meet different counters instead of queueing on the same ones.
+// from row r0, nwords LDS words) into the global counters.  The group's rows
+// are contiguous in the table, so field c of the group (the low or high half
+// of word c / 2) is counter (r0 << log2m) + c: lane l of a wave adds counter
+// base + l, and one atomic instruction covers 64 consecutive counters (eight
+// 64-byte lines).  Blocks of one group flush at about the same time into the
+// same counters; block `rank` of `ranks` starts its pass at its own fraction
+// of the fields.
 template <typename KeyT, typename WT>
 __device__ __forceinline__ void rows_flush(const RowArgs<KeyT, WT>& args, uint32_t r0, const uint32_t* words,
                                            uint32_t nwords, uint32_t rank, uint32_t ranks) {
-  const uint32_t lw = args.log2m - 1;
-  const uint32_t start = (uint32_t)(((uint64_t)nwords * (rank % ranks) / ranks) & ~63ull);
-  for (uint32_t k = threadIdx.x; k < nwords; k += kRowBlock) {
-    const uint32_t i = k + start < nwords ? k + start : k + start - nwords;
-    const uint32_t w = words[i];
-    const uint32_t r = i >> lw, wi = i & ((1u << lw) - 1u);
-    unsigned long long* const p = args.table + ((size_t)(r0 + r) << args.log2m) + 2u * wi;
-    const int32_t lo = (int32_t)(w & 0xFFFFu) - 32768, hi = (int32_t)(w >> 16) - 32768;
-    if (lo) atomicAdd(p, (unsigned long long)(long long)lo);
-    if (hi) atomicAdd(p + 1, (unsigned long long)(long long)hi);
+  const uint32_t nf = 2u * nwords;
+  const uint32_t start = (uint32_t)(((uint64_t)nf * (rank % ranks) / ranks) & ~63ull);
+  unsigned long long* const base = args.table + ((size_t)r0 << args.log2m);
+  for (uint32_t k = threadIdx.x; k < nf; k += kRowBlock) {
+    const uint32_t c = k + start < nf ? k + start : k + start - nf;
+    const int32_t v = (int32_t)((words[c >> 1] >> ((c & 1u) << 4)) & 0xFFFFu) - 32768;
+    if (v) atomicAdd(base + c, (unsigned long long)(long long)v);
   }
 }
 
