@@ -836,6 +836,14 @@ def run_divmod(args, wl):
     elapsed = time.perf_counter() - t0
     M.mersenne_status()
     k_ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
+    # the outputs the oracle checks (before the naive kernel reuses the buffers): the first
+    # 2^22 values (the ones it is timed on) and every (n / 2^20)-th value of the batch
+    n_pre = min(n, 1 << 22)
+    idx = torch.arange(0, n, max(1, n // (1 << 20)), device=dev)
+    check = None
+    if not args.no_cpu_baseline:
+        check = [(x[:n_pre], q[:n_pre], r[:n_pre]), (x[idx], q[idx], r[idx])]
+        check = [tuple(t.cpu().numpy().view(np.uint64) for t in c) for c in check]
     naive_ms = None
     if not args.no_naive:
         nn = min(n, 1 << 24)
@@ -859,15 +867,26 @@ def run_divmod(args, wl):
                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, n),
                         "algorithmic_bytes_per_launch": bytes_per * n, "kernel": "k_divmod",
                         "kernel_avg_ms": round(k_ms, 4), "algorithmic_bytes_per_value": bytes_per}}
-    if not args.no_cpu_baseline:
+    if check is not None:
         import oracle as O
-        nn = 1 << 22
-        xh = x[:nn].cpu().numpy().view(np.uint64)
-        t0 = time.perf_counter()
-        O.divmod_batch(wl["prime"], xh)
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(nn / dt / 1e9, 6), "unit": "Gvalues/s", "cores": 1, "kind": "oracle",
-                               "sample": f"first {nn} values, {dt:.1f} s, one thread"}
+        differ = 0
+        for i, (xh, qg, rg) in enumerate(check):
+            t0 = time.perf_counter()
+            qo, ro = O.divmod_batch(wl["prime"], xh)
+            dt = time.perf_counter() - t0
+            if i == 0:
+                out["cpu_baseline"] = {"value": round(xh.shape[0] / dt / 1e9, 6), "unit": "Gvalues/s", "cores": 1,
+                                       "kind": "oracle",
+                                       "sample": f"first {xh.shape[0]} values, {dt:.1f} s, one thread"}
+            qo, ro = qo.reshape(qg.shape), ro.reshape(rg.shape)
+            differ += int((qo != qg).any(axis=-1).sum() + (ro != rg).any(axis=-1).sum()) if qg.ndim > 1 else \
+                int((qo != qg).sum() + (ro != rg).sum())
+        out["parity"] = {"status": "bit-exact" if differ == 0 else "MISMATCH",
+                         "checked": f"quotient and remainder of the first {n_pre} values and of every "
+                                    f"{max(1, n // (1 << 20))}-th value of the {n} (after the timed launches), "
+                                    f"against the oracle", "values_differing": differ}
+    else:
+        out["parity"] = {"status": "not checked (--no-cpu-baseline)"}
     return out
 
 

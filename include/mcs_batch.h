@@ -38,7 +38,7 @@ typedef struct {
  *   - else with the two-pass update (buckets <= 2^18 and rows <= 16 here).
  * Row-resident and direct members share one persistent launch whose blocks
  * take (sketch, row group, key range) items from a queue, largest first.
- * keys_per_thread: keys per lane of a wave tile in that launch, 4 or 8
+ * keys_per_thread: keys per lane of a wave tile in that launch, 2, 4 or 8
  *   (default 8).
  * lds_chunk_keys: keys per LDS work item (default 65536).
  * combine: the two-pass update combines repeated keys inside tiles (default 1;
@@ -71,7 +71,7 @@ cs_status cs_batch_update(cs_batch* b, hipStream_t stream);
  * be NULL); use_graph is kept.  It first tries every combination of the class
  * limits (row-resident on or off; LDS table limit 8, 20480, 40960, 65536 or
  * 163840 bytes; direct fraction 1/128, 1/8 or 1), then, from the fastest,
- * keys per thread 4 and 8, LDS chunk 2^15 and 2^17 keys and combining on and
+ * keys per thread 2, 4 and 8, LDS chunk 2^15 and 2^17 keys and combining on and
  * off, one knob at a time.  Each candidate is timed as the median of three
  * updates after a warm-up.  The members' counters and flags are copied aside
  * first and put back at the end, so the sketches keep what they held (this

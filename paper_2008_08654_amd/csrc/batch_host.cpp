@@ -73,8 +73,9 @@ cs_status mcs::batch_plan(const cs_batch_item* items, size_t count, int kb, int 
   const uint64_t chunk = opts.lds_chunk_keys ? opts.lds_chunk_keys : kDefaultChunk;
   P.combine = opts.combine >= 0;
   const double direct = opts.direct_fraction == 0.0 ? kDefaultDirect : opts.direct_fraction;
-  if (opts.keys_per_thread != 0 && opts.keys_per_thread != 4 && opts.keys_per_thread != 8)
-    return fail(CS_EINVAL, "keys_per_thread must be 0, 4 or 8");
+  if (opts.keys_per_thread != 0 && opts.keys_per_thread != 2 && opts.keys_per_thread != 4 &&
+      opts.keys_per_thread != 8)
+    return fail(CS_EINVAL, "keys_per_thread must be 0, 2, 4 or 8");
   P.row_kpt = opts.keys_per_thread ? (int)opts.keys_per_thread : 8;
   struct RowMember {
     uint32_t id, rpg, rows, log2m;
@@ -549,7 +550,7 @@ extern "C" cs_status cs_batch_autotune(cs_batch* b, hipStream_t stream, cs_batch
         consider(c);
       }
   // then one knob at a time from the best so far
-  for (uint32_t kpt : {4u, 8u}) {
+  for (uint32_t kpt : {2u, 4u, 8u}) {
     cs_batch_options c = best_opts;
     c.keys_per_thread = kpt;
     consider(c);

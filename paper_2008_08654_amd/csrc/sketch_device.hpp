@@ -1437,7 +1437,10 @@ hipError_t launch_batch_t(const BatchLaunch& b, hipStream_t st) {
     // that a captured graph replays it)
     hipError_t e = launch_fill_zero((unsigned long long*)b.row_queue, 1, st);
     if (e != hipSuccess) return e;
-    if (b.row_kpt == 4)
+    if (b.row_kpt == 2)
+      hipLaunchKernelGGL((k_batch_rows<PRIME, MODE, K, KeyT, WT, 2>), dim3(b.row_blocks), dim3(kRowBlock), 0, st,
+                         b.sketches, b.row_item_list, b.row_items, b.row_queue);
+    else if (b.row_kpt == 4)
       hipLaunchKernelGGL((k_batch_rows<PRIME, MODE, K, KeyT, WT, 4>), dim3(b.row_blocks), dim3(kRowBlock), 0, st,
                          b.sketches, b.row_item_list, b.row_items, b.row_queue);
     else

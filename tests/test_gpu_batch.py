@@ -99,7 +99,7 @@ def test_batch_autotune_keeps_counters_then_exact():
     chosen = b.autotune()
     assert chosen.lds_table_max in (8, 20480, 40960, 65536, 163840)
     assert chosen.direct_fraction in (1.0 / 128, 0.125, 1.0)
-    assert chosen.keys_per_thread in (0, 4, 8) and chosen.row_resident in (1, -1)
+    assert chosen.keys_per_thread in (0, 2, 4, 8) and chosen.row_resident in (1, -1)
     assert b.options().lds_table_max == chosen.lds_table_max
     for (sk, k, w), t in zip(members, want):
         assert np.array_equal(sk.counters(), t), (sk.rows, sk.buckets, k.numel())
@@ -156,6 +156,7 @@ def _row_oracle(prime, mode, spec, k, w):
     (1, 2, "u32", "i64", 8),   # two polynomials
     (2, 1, "u64", "i64", 4),   # 2^89 - 1, Algorithm 3's bit layout
     (1, 3, "u64", "i32", 8),   # any bucket count
+    (1, 0, "u32", "i32", 2),   # two keys per lane
 ])
 def test_batch_row_resident_matches_oracle(prime, mode, kt, wt, kpt):
     """Every member in the one persistent row-resident launch (no LDS class: table limit
