@@ -36,12 +36,14 @@ struct F61 {
   uint32_t w0, w1;
 };
 
-// One Horner step y <- fold(y*x + a) for a key x < 2^32 (Algorithm 1).
-// Preconditions: y < 2^62, a < 2^61.  y*x + a < 2^94, and the fold leaves
-// (P mod 2^61) + (P >> 61) < 2^61 + 2^33 < 2p.
-__device__ __forceinline__ F61 p61_step_x32(F61 y, uint32_t x, F61 a) {
-  uint64_t t = mad64(y.w0, x, a.w0);                       // bits 0..63 partial
-  uint64_t u = mad64(y.w1, x, (uint64_t)hi32(t) + a.w1);   // bits 32..95
+// One Horner step y <- fold(y*x + a) for a key x < 2^32 (Algorithm 1), with
+// the coefficient given as a_lo (its low limb, or that plus one, as a 64-bit
+// value <= 2^32) and a_hi (its high limb, < 2^29).
+// Preconditions: y < 2^62.  y*x + a < 2^94, and the fold leaves
+// (P mod 2^61) + (P >> 61) < 2^61 + 2^34 < 2p.
+__device__ __forceinline__ F61 p61_step_x32(F61 y, uint32_t x, uint64_t a_lo, uint32_t a_hi) {
+  uint64_t t = mad64(y.w0, x, a_lo);                      // < 2^64: bits 0..63 partial
+  uint64_t u = mad64(y.w1, x, (uint64_t)hi32(t) + a_hi);  // bits 32..95
   // P = u * 2^32 + lo32(t);  P & p = (u & (2^29-1)) * 2^32 + lo32(t);  P >> 61 = u >> 29
   uint64_t low = ((uint64_t)(lo32(u) & kMask29) << 32) | lo32(t);
   // keep low as one register pair: the low word is already in t's pair, so
@@ -51,6 +53,15 @@ __device__ __forceinline__ F61 p61_step_x32(F61 y, uint32_t x, F61 a) {
   uint64_t r = low + (u >> 29);
   return F61{lo32(r), hi32(r)};
 }
+__device__ __forceinline__ F61 p61_step_x32(F61 y, uint32_t x, F61 a) { return p61_step_x32(y, x, a.w0, a.w1); }
+
+// The low word of h = v mod p, given r = the last Horner step's fold of
+// y*x + a_0 + 1 (that step run with a_lo = a_0's low limb + 1).  r is congruent
+// to h + 1 with 1 <= r < 2^61 + 2^34 < 2p + 1, so r is h + 1 or h + 1 + p and
+// z = r >> 61 tells which; h = r - z*p - 1, whose low word is
+// lo32(r) + z - 1 (p = 2^32 - 1 modulo 2^32).  This replaces the final
+// reduction (Algorithm 4 for v < 2p) where only the low word is needed.
+__device__ __forceinline__ uint32_t p61_lo_from_inc(F61 r) { return r.w0 + (r.w1 >> 29) - 1u; }
 
 // One Horner step for a key x < 2^60 (two-limb key).  Preconditions: y < 2p,
 // x < 2^60, a < p, so P = y*x + a < p^2 (Algorithm 1's invariant) and the

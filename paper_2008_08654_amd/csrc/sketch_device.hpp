@@ -62,19 +62,36 @@ __device__ __forceinline__ F61 horner61_x32(const RowCoeffs<K, NP>& c, int q, ui
   return y;
 }
 
+// The code (low word of the reduced hash value) of key x < 2^32 under
+// polynomial q: Horner's rule (Algorithm 1) whose last step adds a_0 + 1, then
+// p61_lo_from_inc in place of the final reduction.
+template <int K, int NP>
+__device__ __forceinline__ uint32_t code61_x32(const RowCoeffs<K, NP>& c, int q, uint32_t x) {
+  F61 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
+#pragma unroll
+  for (int i = K - 2; i >= 1; --i) y = p61_step_x32(y, x, F61{c.w[q * K + i][0], c.w[q * K + i][1]});
+  y = p61_step_x32(y, x, (uint64_t)c.w[q * K][0] + 1u, c.w[q * K][1]);
+  return p61_lo_from_inc(y);
+}
+
 // The same for two keys, their steps interleaved: the two chains are
 // independent, so each fills the other's dependency stalls.
 template <int K, int NP>
-__device__ __forceinline__ void horner61_x32_pair(const RowCoeffs<K, NP>& c, int q, uint32_t xa, uint32_t xb, F61& ya,
-                                                  F61& yb) {
-  ya = F61{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
-  yb = ya;
+__device__ __forceinline__ void code61_x32_pair(const RowCoeffs<K, NP>& c, int q, uint32_t xa, uint32_t xb,
+                                                uint32_t& ca, uint32_t& cb) {
+  F61 ya{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
+  F61 yb = ya;
 #pragma unroll
-  for (int i = K - 2; i >= 0; --i) {
+  for (int i = K - 2; i >= 1; --i) {
     const F61 a{c.w[q * K + i][0], c.w[q * K + i][1]};
     ya = p61_step_x32(ya, xa, a);
     yb = p61_step_x32(yb, xb, a);
   }
+  const uint64_t a0 = (uint64_t)c.w[q * K][0] + 1u;
+  ya = p61_step_x32(ya, xa, a0, c.w[q * K][1]);
+  yb = p61_step_x32(yb, xb, a0, c.w[q * K][1]);
+  ca = p61_lo_from_inc(ya);
+  cb = p61_lo_from_inc(yb);
 }
 
 template <int K, int NP>
@@ -166,7 +183,10 @@ __device__ __forceinline__ void bucket_sign(const RowCoeffs<K, NP>& c, uint32_t 
 template <int PRIME, int MODE, int K, bool WIDE, int NP>
 __device__ __forceinline__ uint32_t bucket_code(const RowCoeffs<K, NP>& c, uint32_t x0, uint32_t x1, uint32_t log2m) {
   if constexpr (PRIME == kPrime61 && MODE == kTwoForOne) {
-    return p61_final_lo(WIDE ? horner61_x64<K, NP>(c, 0, x0, x1) : horner61_x32<K, NP>(c, 0, x0));
+    if constexpr (WIDE)
+      return p61_final_lo(horner61_x64<K, NP>(c, 0, x0, x1));
+    else
+      return code61_x32<K, NP>(c, 0, x0);
   } else if constexpr (PRIME == kPrime89 && MODE == kTwoForOne) {
     return hash89<K, NP>(c, 0, x0, x1).w0;
   } else {
@@ -257,7 +277,11 @@ __device__ __forceinline__ void tile_issue(const KeyT* __restrict__ kp, const WT
 }
 
 // Splits loaded keys into 32-bit limbs and weights into 32 bits.  big: some
-// weight is outside (-2^15, 2^15); any_hi: the or of the keys' high words.
+// weight does not fit 32 bits (never, for 32-bit weights); any_hi: the
+// largest of the keys' high words (zero iff every key has one limb; its bits
+// from 28 on tell a key >= 2^60).  A maximum, not an or: the compiler turns
+// an or of high words into an or of whole keys and a compare, twice the
+// instructions.
 template <int kKpt, typename KeyT, typename WT>
 __device__ __forceinline__ void tile_unpack(const KeyT (&kr)[kKpt], const WT (&wr)[kKpt], uint32_t (&x0)[kKpt],
                                             uint32_t (&x1)[kKpt], int32_t (&wf)[kKpt], bool& big, uint32_t& any_hi) {
@@ -266,11 +290,8 @@ __device__ __forceinline__ void tile_unpack(const KeyT (&kr)[kKpt], const WT (&w
     const uint64_t k = (uint64_t)kr[j];
     x0[j] = (uint32_t)k;
     x1[j] = (uint32_t)(k >> 32);
-    any_hi |= x1[j];
-    if constexpr (sizeof(WT) == 4)
-      big |= (uint32_t)((int32_t)wr[j] + 32767) > 65534u;
-    else
-      big |= (uint64_t)((int64_t)wr[j] + 32767) > 65534u;
+    any_hi = x1[j] > any_hi ? x1[j] : any_hi;
+    if constexpr (sizeof(WT) == 8) big |= (int64_t)(int32_t)wr[j] != (int64_t)wr[j];
     wf[j] = (int32_t)wr[j];
   }
 }
@@ -417,18 +438,23 @@ __global__ __launch_bounds__(kBlock) void k_update_global(UpdateArgs<KeyT, WT> a
 // counters with device-scope atomics: +-2^16 on its own bucket and, for a low
 // field, the carry c that went into the high half (-c on the high bucket,
 // +-2^16 more if that carry wrapped the high half out of the word).  A field
-// must drift 2^15 from its bias to wrap, so these adds are rare.  At the end
+// must drift 2^15 from its bias to wrap, so these adds are rare for small
+// weights; a weight of 2^15 or more always wraps its field and takes that
+// path, which is exact for every 32-bit weight (the LDS add is exact modulo
+// 2^32 and the carried multiples of 2^16 are taken in 64 bits).  At the end
 // each block adds field - 2^15 of every non-zero field into the global
 // counters.  Every step is an integer add, so the counters are exact in any
-// order.  Weights with |w| >= 2^15 skip the fields and go to the global
-// counters directly.
+// order.  64-bit weights that do not fit 32 bits skip the fields and go to
+// the global counters directly.
 // ---------------------------------------------------------------------------
 // The rows of a row group for one wave's keys: hash, add each s*w into its
 // field, carry wraps into the global counters.  ESC: some keys have weights
 // that bypass the fields (esc[j]); without ESC every wf[j] is the key's weight.
 // One row (local index r of the block's group, global index row, coefficients
-// c) for one wave's keys.
-template <int PRIME, int MODE, int K, int NP, bool WIDE, bool ESC, int NK, typename KeyT, typename WT>
+// c) for one wave's keys.  ROW0: r is 0 (the block's group is one row), so the
+// LDS address is the code's bucket bits alone.
+template <int PRIME, int MODE, int K, int NP, bool WIDE, bool ESC, int NK, bool ROW0 = false, typename KeyT,
+          typename WT>
 __device__ __forceinline__ void row_update(const RowArgs<KeyT, WT>& args, const RowCoeffs<K, NP>& c, uint32_t row,
                                            uint32_t r, uint32_t* words, const uint32_t (&x0)[NK],
                                            const uint32_t (&x1)[NK], const int32_t (&wf)[NK],
@@ -438,18 +464,15 @@ __device__ __forceinline__ void row_update(const RowArgs<KeyT, WT>& args, const 
   {
     // byte offset of the row in LDS, a multiple of 2m, or-ed onto code & amask;
     // kept in a vector register so that the and-or takes one instruction
-    uint32_t rowoff;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(rowoff) : "s"(r * 2u * m));
+    uint32_t rowoff = 0;
+    if (!ROW0) asm volatile("v_mov_b32 %0, %1" : "=v"(rowoff) : "s"(r * 2u * m));
     uint32_t code[NK], old[NK], sh[NK];
     int32_t sw[NK];
     if constexpr (PRIME == kPrime61 && MODE == kTwoForOne && !WIDE && NK % 2 == 0) {
       // the low-bit split: the code is the low word of the reduced hash
 #pragma unroll
       for (int j = 0; j < NK; j += 2) {
-        F61 ya, yb;
-        horner61_x32_pair<K, NP>(c, 0, x0[j], x0[j + 1], ya, yb);
-        code[j] = p61_final_lo(ya);
-        code[j + 1] = p61_final_lo(yb);
+        code61_x32_pair<K, NP>(c, 0, x0[j], x0[j + 1], code[j], code[j + 1]);
       }
     } else {
 #pragma unroll
@@ -464,6 +487,10 @@ __device__ __forceinline__ void row_update(const RowArgs<KeyT, WT>& args, const 
       sh[j] = (code[j] & 2u) << 3;
       old[j] = atomicAdd((uint32_t*)((unsigned char*)words + ((code[j] & amask) | rowoff)), (uint32_t)sw[j] << sh[j]);
     }
+    // The field wrapped iff its old value plus s*w leaves [0, 2^16).  Taken in
+    // 32 bits this test is exact for every 32-bit weight: the true sum lies in
+    // [-2^31, 2^31 + 2^16), and no value there outside [0, 2^16) is congruent
+    // modulo 2^32 to one inside.
     bool wr[NK];
     bool any_wr = false;
 #pragma unroll
@@ -477,13 +504,22 @@ __device__ __forceinline__ void row_update(const RowArgs<KeyT, WT>& args, const 
 #pragma unroll
       for (int j = 0; j < NK; ++j)
         if (wr[j]) {
+          // In 64 bits: s*w is 2^31 for w = -2^31, and a weight of many times
+          // 2^16 moves the field by many multiples of 2^16.  The 32-bit add in
+          // LDS was exact modulo 2^32, so the field (and, for the low half,
+          // the high half above it) now holds the sum modulo 2^16; cw
+          // multiples of 2^16 went missing from the field (floor division),
+          // and for the low half they went into the high half instead.
           const uint32_t bucket = (code[j] >> 1) & (m - 1u);
-          const int32_t t = (int32_t)__builtin_amdgcn_ubfe(old[j], sh[j], 16u) + sw[j];
-          const int32_t cw = t >> 16;  // -1 or +1: the field lost -cw * 2^16
-          atomicAdd(&grow[bucket], (unsigned long long)((long long)cw * 65536));
-          if (sh[j] == 0) {  // the low half's carry went into the high half
-            const int32_t e = ((int32_t)(old[j] >> 16) + cw) >> 16;  // -1, 0 or +1
-            atomicAdd(&grow[bucket + 1], (unsigned long long)((long long)e * 65536 - cw));
+          // s*w from the 32-bit sw: only s = -1, w = -2^31 gives 2^31, which
+          // 32 bits hold as -2^31
+          const int64_t swl = (code[j] & 1u) && sw[j] == INT32_MIN ? (int64_t)1 << 31 : (int64_t)sw[j];
+          const int64_t t = (int64_t)__builtin_amdgcn_ubfe(old[j], sh[j], 16u) + swl;
+          const int64_t cw = t >> 16;
+          atomicAdd(&grow[bucket], (unsigned long long)(cw * 65536));
+          if (sh[j] == 0) {  // the high half received cw and lost e multiples of 2^16
+            const int64_t e = ((int64_t)(old[j] >> 16) + cw) >> 16;
+            atomicAdd(&grow[bucket + 1], (unsigned long long)(e * 65536 - cw));
           }
         }
     }
@@ -533,7 +569,7 @@ __device__ __forceinline__ uint32_t rows_wave_tile_slow(const RowArgs<KeyT, WT>&
 #pragma unroll
     for (int j = 0; j < NK; ++j) {
       any_hi |= x1[j];
-      const bool fits = wv[j] > -32768 && wv[j] < 32768;
+      const bool fits = wv[j] == (int64_t)(int32_t)wv[j];
       wf[j] = ok[j] && fits ? (int32_t)wv[j] : 0;  // positions past n add 0
       esc[j] = ok[j] && !fits;
       any_e |= esc[j];
@@ -573,7 +609,7 @@ __device__ __forceinline__ uint32_t rows_wave_tile(const RowArgs<KeyT, WT>& args
         for (int j = 0; j < KPT; ++j) x1[j] = 0;  // the one-limb hash reads no high words
       }
       if (one)
-        row_update<PRIME, MODE, K, NP, false, false, KPT>(args, c1, r0, 0, words, x0, x1, wf, nullptr, nullptr,
+        row_update<PRIME, MODE, K, NP, false, false, KPT, true>(args, c1, r0, 0, words, x0, x1, wf, nullptr, nullptr,
                                                           false);
       else
         rows_tile<PRIME, MODE, K, NP, false, false, KPT>(args, r0, words, x0, x1, wf, nullptr, nullptr, false);
@@ -602,6 +638,18 @@ __device__ __forceinline__ void rows_flush(const RowArgs<KeyT, WT>& args, uint32
     const int32_t v = (int32_t)((words[c >> 1] >> ((c & 1u) << 4)) & 0xFFFFu) - 32768;
     if (v) atomicAdd(base + c, (unsigned long long)(long long)v);
   }
+}
+
+// atomicAdd(p, v) whose result is waited for only where it is used.  With a
+// uniform address the compiler's atomic optimizer rewrites an atomic into one
+// per wave whose old value is broadcast to the lanes at once, which waits for
+// the round trip right there; an address the compiler cannot prove uniform
+// (p plus a zero it cannot see) keeps the atomic as written, so the value can
+// be taken ahead of its use.
+__device__ __forceinline__ uint32_t atomic_add_ahead(uint32_t* p, uint32_t v) {
+  uint32_t zero;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+  return atomicAdd(p + zero, v);
 }
 
 // The wave tiles are cut into contiguous ranges, one per XCD plus a pool, and
@@ -669,12 +717,12 @@ __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> arg
     // the next chunk is taken before the current one is processed, so the
     // atomic's round trip overlaps the hashing
     uint32_t next = 0;
-    if (lane == 0) next = atomicAdd(q, 1u);
+    if (lane == 0) next = atomic_add_ahead(q, 1u);
     for (;;) {
       const uint32_t c = __builtin_amdgcn_readfirstlane(next);
       const uint64_t wt0 = lo + (uint64_t)c * kRowChunk;
       if (wt0 >= hi) break;
-      if (lane == 0) next = atomicAdd(q, 1u);
+      if (lane == 0) next = atomic_add_ahead(q, 1u);
       const uint64_t wt1 = wt0 + kRowChunk < hi ? wt0 + kRowChunk : hi;
       for (uint64_t wt = wt0; wt < wt1; ++wt) {
         KeyT ka[kRowKpt];
@@ -754,7 +802,7 @@ __global__ __launch_bounds__(kRowBlock) void k_batch_rows(const BatchSketch* __r
   __syncthreads();  // read by all before the fields are set
   while (it < nitems) {
     uint32_t pre = 0;
-    if (threadIdx.x == 0) pre = atomicAdd(queue, 1u);
+    if (threadIdx.x == 0) pre = atomic_add_ahead(queue, 1u);
     const BatchRowItem item = uniform_load(items + it);
     const BatchSketch sk = uniform_load(sks + item.sketch);
     const RowArgs<KeyT, WT> a{(const KeyT*)sk.keys, (const WT*)sk.weights, sk.n, sk.coeffs, sk.rows, sk.log2m,
