@@ -115,8 +115,10 @@ struct F89 {
 // One Horner step y <- fold(y*x + a) for a 64-bit key x = (x1:x0).
 // Preconditions: y < 2p, a < p: P = y*x + a < p^2 (p >= 2u - 1 with u = 2^64),
 // P < 2^154 in five limbs; the fold leaves (P mod 2^89) + (P >> 89) < 2p.
-__device__ __forceinline__ F89 p89_step(F89 y, uint32_t x0, uint32_t x1, F89 a) {
-  uint64_t t = mad64(y.w0, x0, a.w0);
+// a_lo is the coefficient's low limb (or that plus one, <= 2^32), as in
+// p61_step_x32; y*x + a + 1 <= p^2 keeps the bound.
+__device__ __forceinline__ F89 p89_step(F89 y, uint32_t x0, uint32_t x1, F89 a, uint64_t a_lo) {
+  uint64_t t = mad64(y.w0, x0, a_lo);
   uint32_t p0 = lo32(t);
   t = mad64(y.w0, x1, (uint64_t)hi32(t) + a.w1);  // <= 2^64 - 2^33 + 1 + 2^33 - 2
   uint64_t u = mad64(y.w1, x0, lo32(t));
@@ -137,6 +139,12 @@ __device__ __forceinline__ F89 p89_step(F89 y, uint32_t x0, uint32_t x1, F89 a) 
   uint32_t r2 = (p2 & kMask25) + h2 + hi32(s);
   return F89{r0, r1, r2};
 }
+
+__device__ __forceinline__ F89 p89_step(F89 y, uint32_t x0, uint32_t x1, F89 a) { return p89_step(y, x0, x1, a, a.w0); }
+
+// The low word of h = v mod p from r = the last step's fold of y*x + a_0 + 1,
+// as p61_lo_from_inc: 1 <= r < 2^89 + 2^65 < 2p + 1, z = r >> 89 in {0, 1}.
+__device__ __forceinline__ uint32_t p89_lo_from_inc(F89 r) { return r.w0 + (r.w2 >> 25) - 1u; }
 
 // y < 2p -> y mod p, branch-free (z = (y+1) >> 89 in {0,1}; (y+z) & p).
 __device__ __forceinline__ F89 p89_final(F89 y) {

@@ -121,13 +121,35 @@ __device__ __forceinline__ F89 hash89(const RowCoeffs<K, NP>& c, int q, uint32_t
   return p89_final(y);
 }
 
+// The low word of the reduced hash value of key (x0, x1) over 2^89 - 1, as
+// code61_x32.
+template <int K, int NP>
+__device__ __forceinline__ uint32_t code89(const RowCoeffs<K, NP>& c, int q, uint32_t x0, uint32_t x1) {
+  F89 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1], c.w[q * K + K - 1][2]};
+#pragma unroll
+  for (int i = K - 2; i >= 1; --i)
+    y = p89_step(y, x0, x1, F89{c.w[q * K + i][0], c.w[q * K + i][1], c.w[q * K + i][2]});
+  y = p89_step(y, x0, x1, F89{c.w[q * K][0], c.w[q * K][1], c.w[q * K][2]}, (uint64_t)c.w[q * K][0] + 1u);
+  return p89_lo_from_inc(y);
+}
+
 // Bucket and sign bit of key (x0, x1) under a row's coefficients.  WIDE
 // selects the two-limb key path for p61.
 template <int PRIME, int MODE, int K, bool WIDE, int NP>
 __device__ __forceinline__ void bucket_sign(const RowCoeffs<K, NP>& c, uint32_t x0, uint32_t x1, uint32_t log2m,
                                             uint32_t& bucket, uint32_t& a) {
   const uint32_t mask = (1u << log2m) - 1u;
-  if constexpr (PRIME == kPrime61) {
+  if constexpr (PRIME == kPrime61 && !WIDE && (MODE == kTwoForOne || MODE == kTwoPoly)) {
+    // these splits read only low bits of the hash values
+    const uint32_t h = code61_x32<K, NP>(c, 0, x0);
+    if constexpr (MODE == kTwoForOne) {
+      a = h & 1u;
+      bucket = (h >> 1) & mask;
+    } else {
+      a = code61_x32<K, NP>(c, 1, x0) & 1u;
+      bucket = h & mask;
+    }
+  } else if constexpr (PRIME == kPrime61) {
     uint64_t h = WIDE ? hash61_x64<K, NP>(c, 0, x0, x1) : hash61_x32<K, NP>(c, 0, x0);
     if constexpr (MODE == kTwoForOne) {
       a = (uint32_t)h & 1u;
@@ -150,15 +172,22 @@ __device__ __forceinline__ void bucket_sign(const RowCoeffs<K, NP>& c, uint32_t 
       a = (uint32_t)h2 & 1u;
       bucket = (uint32_t)h & mask;
     }
+  } else if constexpr (MODE == kTwoForOne || MODE == kTwoPoly) {
+    // over 2^89 - 1 too these splits read only the low words
+    const uint32_t h = code89<K, NP>(c, 0, x0, x1);
+    if constexpr (MODE == kTwoForOne) {
+      a = h & 1u;
+      bucket = (h >> 1) & mask;
+    } else {
+      a = code89<K, NP>(c, 1, x0, x1) & 1u;
+      bucket = h & mask;
+    }
   } else {
     F89 h = hash89<K, NP>(c, 0, x0, x1);
-    if constexpr (MODE == kTwoForOne) {
-      a = h.w0 & 1u;
-      bucket = (h.w0 >> 1) & mask;
-    } else if constexpr (MODE == kTwoForOneMsb) {
+    if constexpr (MODE == kTwoForOneMsb) {
       a = (h.w2 >> 24) & 1u;
       bucket = h.w0 & mask;
-    } else if constexpr (MODE == kArbR) {
+    } else {  // kArbR
       // Algorithm 8 with b = 89: h+1 in 32-bit limbs, sign bit 88, and
       // floor(r j / 2^88) for the low 88 bits j (three 32x32 products).
       const uint64_t s0 = (uint64_t)h.w0 + 1u;
@@ -169,10 +198,6 @@ __device__ __forceinline__ void bucket_sign(const RowCoeffs<K, NP>& c, uint32_t 
       const uint64_t t1 = (uint64_t)(uint32_t)s1 * c.r + (t0 >> 32);
       const uint64_t t2 = (uint64_t)(x2 & 0xFFFFFFu) * c.r + (t1 >> 32);
       bucket = (uint32_t)(t2 >> 24);
-    } else {
-      F89 h2 = hash89<K, NP>(c, 1, x0, x1);
-      a = h2.w0 & 1u;
-      bucket = h.w0 & mask;
     }
   }
 }
@@ -188,7 +213,11 @@ __device__ __forceinline__ uint32_t bucket_code(const RowCoeffs<K, NP>& c, uint3
     else
       return code61_x32<K, NP>(c, 0, x0);
   } else if constexpr (PRIME == kPrime89 && MODE == kTwoForOne) {
-    return hash89<K, NP>(c, 0, x0, x1).w0;
+    return code89<K, NP>(c, 0, x0, x1);
+  } else if constexpr (PRIME == kPrime61 && MODE == kTwoPoly && !WIDE) {
+    // bucket from h1's low bits, sign from bit 0 of h2; bits above the bucket
+    // may hold anything
+    return (code61_x32<K, NP>(c, 0, x0) << 1) | (code61_x32<K, NP>(c, 1, x0) & 1u);
   } else {
     uint32_t bk, a;
     bucket_sign<PRIME, MODE, K, WIDE, NP>(c, x0, x1, log2m, bk, a);
