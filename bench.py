@@ -34,25 +34,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # ALU peak, from the unit counts: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.64 T lane-slots/s
-# (the fp32 vector peak of 157.3 TFLOP/s is this many fused multiply-adds).  A 32-bit
-# integer VALU instruction takes one slot per lane; the 64-bit ones of the hash
-# (v_mad_u64_u32, v_lshl_add_u64, v_lshrrev_b64) take two: measured by
-# `bench.py --workload ceilings` (profiles/ceilings.md) at 36.8-37.6 T lane-instructions/s
-# against 69.5 T for v_add_u32.
+# (the fp32 vector peak of 157.3 TFLOP/s is this many fused multiply-adds).  Measured by
+# `bench.py --workload ceilings` (profiles/ceilings.md): a SIMD issues one wave64 VALU
+# instruction per slot, 64 lane-operations where the peak counts 128; only the simple
+# two-operand 32-bit operations (add, sub, and, xor, mov) issue two per slot, from two
+# waves.  So an instruction costs 2 lane-slots (64-bit v_mad_u64_u32, v_lshl_add_u64,
+# v_lshrrev_b64, and 32-bit shifts, bit-field extracts, three-input and carry
+# instructions alike: 36.9-37.8 T lane-instructions/s each) and a simple one 1 (69.6 T).
 VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12  # 78.64 T lane-slots/s
 HBM_PEAK_GBS = 8000.0
 METRIC = "Gkeys/s into Count Sketch (p=2^61-1, 4-universal) + % of binding roofline"
 
-# Algorithmic VALU slots per key and row: the VALU instructions (register moves not
+# Algorithmic VALU lane-slots per key and row: the VALU instructions (register moves not
 # counted, so a lower bound) of the compiled straight-line hash + final reduction +
-# split of one row on gfx950, 64-bit instructions weighted 2, plus 2 per row for the
-# signed weight and the counter address (profiles/valu_ops_per_key_row.md):
-#   p61, key < 2^32, two-for-one: 16 64-bit + 6 32-bit = 38, + 2 = 40
-#   p61 two polynomials: 32 64-bit + 9 32-bit = 73, + 2 = 75
-#   p61 any bucket count (Algorithm 8): 18 64-bit + 7 32-bit = 43, + 2 = 45
-#   p89, 64-bit keys, two-for-one: 41 64-bit + 19 32-bit = 101, + 2 = 103
-OPS_PER_KEY_ROW = {("p61", 0): 40, ("p61", 2): 75, ("p89", 0): 103, ("p61", 3): 45}
-OPS_PER_KEY = 3  # weight negation (2) and domain check (1), 32-bit
+# split of one row on gfx950, each weighted by its measured issue cost (2, or 1 for the
+# simple ones), plus 3 per row for the signed weight (v_xad_u32, 2) and the counter
+# address (v_and_b32, 1) (profiles/valu_ops_per_key_row.md):
+#   p61, key < 2^32, two-for-one: 15 64-bit + 4 other + 2 simple = 40, + 3 = 43
+#   p61 two polynomials: 30 64-bit + 5 other + 5 simple = 75, + 3 = 78
+#   p61 any bucket count (Algorithm 8): 18 64-bit + 4 other + 3 simple = 47, + 3 = 50
+#   p89, 64-bit keys, two-for-one: 39 64-bit + 16 other + 2 simple = 112, + 3 = 115
+OPS_PER_KEY_ROW = {("p61", 0): 43, ("p61", 2): 78, ("p89", 0): 115, ("p61", 3): 50}
+OPS_PER_KEY = 3  # the key's high-word test (domain check, one-limb path) and load addressing
 
 SKETCH_WORKLOADS = {
     "single_stream_zipf": dict(n=1 << 28, rows=9, log2m=16, mode=0, prime="p61", keys="zipf", kbytes=8, wbytes=4,
@@ -766,6 +769,11 @@ CEILING_PROBES = [  # (probe id, name, unit of one operation, iters, buffer byte
     (10, "v_bfe_u32", "lane-instructions", 2000, 8),
     (11, "v_and_or_b32", "lane-instructions", 2000, 8),
     (12, "v_xad_u32", "lane-instructions", 2000, 8),
+    (13, "v_lshlrev_b32 (two-operand)", "lane-instructions", 2000, 8),
+    (14, "v_and_b32 (two-operand)", "lane-instructions", 2000, 8),
+    (15, "v_add_co_u32 + v_addc_co_u32", "lane-instructions", 2000, 8),
+    (16, "v_add_u32, one wave per SIMD", "lane-instructions", 2000, 8),
+    (17, "v_mad_u64_u32 and v_add_u32 in turn", "lane-instructions", 2000, 8),
 ]
 
 

@@ -28,7 +28,12 @@ typedef enum {
   CS_CEIL_MOV_B32 = 9,                 /* v_mov_b32 (register copy) */
   CS_CEIL_BFE_U32 = 10,                /* v_bfe_u32 (a three-operand 32-bit instruction) */
   CS_CEIL_AND_OR_B32 = 11,             /* v_and_or_b32 */
-  CS_CEIL_XAD_U32 = 12                 /* v_xad_u32 */
+  CS_CEIL_XAD_U32 = 12,                /* v_xad_u32 */
+  CS_CEIL_LSHLREV_B32 = 13,            /* v_lshlrev_b32 (a two-operand shift) */
+  CS_CEIL_AND_B32 = 14,                /* v_and_b32 (two-operand) */
+  CS_CEIL_ADD_CO_U32 = 15,             /* v_add_co_u32 and v_addc_co_u32 in turn (a 64-bit add in two) */
+  CS_CEIL_ADD32_ONE_WAVE = 16,         /* v_add_u32 with one wave per SIMD (1 block per CU) */
+  CS_CEIL_MIX_MAD_ADD = 17             /* v_mad_u64_u32 and v_add_u32 in turn */
 } cs_ceiling;
 
 /* Enqueues one launch of probe `probe` on `stream` and writes to *ops (host)
@@ -40,7 +45,8 @@ typedef enum {
  *                  int64 counters for the global-atomic probes (zeroed by the
  *                  caller if their values matter)
  *   iters          loop trips per thread (issue, LDS and atomic probes)
- * The probes run 8 blocks of 256 threads per compute unit.  Returns CS_EINVAL
+ * The probes run 8 blocks of 256 threads per compute unit (8 waves per SIMD),
+ * CS_CEIL_ADD32_ONE_WAVE one block per compute unit.  Returns CS_EINVAL
  * for an unknown probe or a buffer too small for it. */
 cs_status cs_ceiling_run(int probe, void* buffer, uint64_t bytes, uint32_t iters, uint64_t* ops, hipStream_t stream);
 

@@ -47,8 +47,25 @@ __global__ __launch_bounds__(kCeilBlock) void k_issue(uint32_t iters, uint64_t* 
           asm volatile("v_bfe_u32 %0, %0, %1, 16" : "+v"(b[i]) : "v"(x));
         else if constexpr (OP == CS_CEIL_AND_OR_B32)
           asm volatile("v_and_or_b32 %0, %0, %1, %2" : "+v"(b[i]) : "v"(x), "v"(y));
-        else
+        else if constexpr (OP == CS_CEIL_XAD_U32)
           asm volatile("v_xad_u32 %0, %0, %1, %2" : "+v"(b[i]) : "v"(x), "v"(y));
+        else if constexpr (OP == CS_CEIL_LSHLREV_B32)
+          asm volatile("v_lshlrev_b32_e32 %0, %1, %0" : "+v"(b[i]) : "v"(x));
+        else if constexpr (OP == CS_CEIL_AND_B32)
+          asm volatile("v_and_b32_e32 %0, %1, %0" : "+v"(b[i]) : "v"(x));
+        else if constexpr (OP == CS_CEIL_ADD_CO_U32) {
+          if (i & 1)
+            asm volatile("v_addc_co_u32_e32 %0, vcc, %1, %0, vcc" : "+v"(b[i]) : "v"(x) : "vcc");
+          else
+            asm volatile("v_add_co_u32_e32 %0, vcc, %1, %0" : "+v"(b[i]) : "v"(x) : "vcc");
+        } else if constexpr (OP == CS_CEIL_ADD32_ONE_WAVE)
+          asm volatile("v_add_u32 %0, %0, %1" : "+v"(b[i]) : "v"(x));
+        else {  // CS_CEIL_MIX_MAD_ADD
+          if (i & 1)
+            asm volatile("v_add_u32 %0, %0, %1" : "+v"(b[i]) : "v"(x));
+          else
+            asm volatile("v_mad_u64_u32 %0, vcc, %1, %2, %0" : "+v"(a[i]) : "v"(x), "v"(y) : "vcc");
+        }
       }
     }
   }
@@ -136,7 +153,12 @@ extern "C" cs_status cs_ceiling_run(int probe, void* buffer, uint64_t bytes, uin
     case CS_CEIL_MOV_B32:
     case CS_CEIL_BFE_U32:
     case CS_CEIL_AND_OR_B32:
-    case CS_CEIL_XAD_U32: {
+    case CS_CEIL_XAD_U32:
+    case CS_CEIL_LSHLREV_B32:
+    case CS_CEIL_AND_B32:
+    case CS_CEIL_ADD_CO_U32:
+    case CS_CEIL_ADD32_ONE_WAVE:
+    case CS_CEIL_MIX_MAD_ADD: {
       if (iters == 0) return fail(CS_EINVAL, "iters must be positive");
       uint64_t* sink = (uint64_t*)buffer;
       if (!sink || bytes < 8) return fail(CS_EINVAL, "the issue probes need an 8-byte device buffer");
@@ -154,9 +176,20 @@ extern "C" cs_status cs_ceiling_run(int probe, void* buffer, uint64_t bytes, uin
         hipLaunchKernelGGL(k_issue<CS_CEIL_BFE_U32>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
       else if (probe == CS_CEIL_AND_OR_B32)
         hipLaunchKernelGGL(k_issue<CS_CEIL_AND_OR_B32>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
-      else
+      else if (probe == CS_CEIL_XAD_U32)
         hipLaunchKernelGGL(k_issue<CS_CEIL_XAD_U32>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
-      count = (uint64_t)grid * kCeilBlock * iters * kChains * kUnroll;  // lane-instructions
+      else if (probe == CS_CEIL_LSHLREV_B32)
+        hipLaunchKernelGGL(k_issue<CS_CEIL_LSHLREV_B32>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
+      else if (probe == CS_CEIL_AND_B32)
+        hipLaunchKernelGGL(k_issue<CS_CEIL_AND_B32>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
+      else if (probe == CS_CEIL_ADD_CO_U32)
+        hipLaunchKernelGGL(k_issue<CS_CEIL_ADD_CO_U32>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
+      else if (probe == CS_CEIL_ADD32_ONE_WAVE)
+        hipLaunchKernelGGL(k_issue<CS_CEIL_ADD32_ONE_WAVE>, dim3(cus), dim3(kCeilBlock), 0, stream, iters, sink);
+      else
+        hipLaunchKernelGGL(k_issue<CS_CEIL_MIX_MAD_ADD>, dim3(grid), dim3(kCeilBlock), 0, stream, iters, sink);
+      count = (uint64_t)(probe == CS_CEIL_ADD32_ONE_WAVE ? cus : grid) * kCeilBlock * iters * kChains *
+              kUnroll;  // lane-instructions
       break;
     }
     case CS_CEIL_HBM_READ: {
