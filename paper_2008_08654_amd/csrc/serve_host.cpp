@@ -45,6 +45,7 @@ constexpr size_t kListsInit = 4u << 20;
 constexpr size_t kResultWords = 32768;  // pinned int64 F2 outputs per step
 constexpr int kDepth = 2;               // steps in flight
 constexpr size_t kScanMax = 16384;      // queued requests one step looks at
+constexpr int kIdlePollUs = 100;        // an idle worker looks at the queue this often
 // Served tables are mostly far larger than the last-level cache, where
 // random 64-bit atomics cost much more than pass 2's coalesced flushes: only
 // the shortest updates take them.
@@ -327,7 +328,11 @@ void worker_main(cs_server* S) {
       if (S->queue.empty()) {
         if (inflight.empty()) {
           if (S->stop) break;
-          S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+          // A timed wait: waking a thread blocked without a timeout took
+          // 2-4 ms here, which the first requests after an idle spell paid
+          // in full (and the queue they built up made the next steps large).
+          S->cv_work.wait_for(lk, std::chrono::microseconds(kIdlePollUs),
+                              [&] { return S->stop || !S->queue.empty(); });
         } else {
           // a step is running: wake for a new arrival or to poll its event
           S->cv_work.wait_for(lk, std::chrono::microseconds(20), [&] { return !S->queue.empty(); });
