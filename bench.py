@@ -47,14 +47,15 @@ METRIC = "Gkeys/s into Count Sketch (p=2^61-1, 4-universal) + % of binding roofl
 
 # Algorithmic VALU lane-slots per key and row: the VALU instructions (register moves not
 # counted, so a lower bound) of the compiled straight-line hash + final reduction +
-# split of one row on gfx950, each weighted by its measured issue cost (2, or 1 for the
-# simple ones), plus 3 per row for the signed weight (v_xad_u32, 2) and the counter
-# address (v_and_b32, 1) (profiles/valu_ops_per_key_row.md):
-#   p61, key < 2^32, two-for-one: 15 64-bit + 4 other + 2 simple = 40, + 3 = 43
-#   p61 two polynomials: 30 64-bit + 5 other + 5 simple = 75, + 3 = 78
-#   p61 any bucket count (Algorithm 8): 18 64-bit + 4 other + 3 simple = 47, + 3 = 50
+# split of one row on gfx950, as the update kernels run it (the Horner steps before the
+# last fold at bit 64; the rare carry path left out), each weighted by its measured issue
+# cost (2, or 1 for the simple ones), plus 3 per row for the signed weight (v_xad_u32, 2)
+# and the counter address (v_and_b32, 1) (profiles/valu_ops_per_key_row.md):
+#   p61, key < 2^32, two-for-one: 13 64-bit + 4 other + 0 simple = 34, + 3 = 37
+#   p61 two polynomials: 26 64-bit + 5 other + 1 simple = 63, + 3 = 66
+#   p61 any bucket count (Algorithm 8): 16 64-bit + 4 other + 1 simple = 41, + 3 = 44
 #   p89, 64-bit keys, two-for-one: 39 64-bit + 16 other + 2 simple = 112, + 3 = 115
-OPS_PER_KEY_ROW = {("p61", 0): 43, ("p61", 2): 78, ("p89", 0): 115, ("p61", 3): 50}
+OPS_PER_KEY_ROW = {("p61", 0): 37, ("p61", 2): 66, ("p89", 0): 115, ("p61", 3): 44}
 OPS_PER_KEY = 3  # the key's high-word test (domain check, one-limb path) and load addressing
 
 SKETCH_WORKLOADS = {

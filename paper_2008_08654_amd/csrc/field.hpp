@@ -39,8 +39,8 @@ struct F61 {
 // One Horner step y <- fold(y*x + a) for a key x < 2^32 (Algorithm 1), with
 // the coefficient given as a_lo (its low limb, or that plus one, as a 64-bit
 // value <= 2^32) and a_hi (its high limb, < 2^29).
-// Preconditions: y < 2^62.  y*x + a < 2^94, and the fold leaves
-// (P mod 2^61) + (P >> 61) < 2^61 + 2^34 < 2p.
+// Preconditions: y < 2^64 (then u = y1*x + t_hi + a_hi < 2^64).  The fold
+// leaves (P mod 2^61) + (P >> 61) < 2^61 + 2^35 < 2p.
 __device__ __forceinline__ F61 p61_step_x32(F61 y, uint32_t x, uint64_t a_lo, uint32_t a_hi) {
   uint64_t t = mad64(y.w0, x, a_lo);                      // < 2^64: bits 0..63 partial
   uint64_t u = mad64(y.w1, x, (uint64_t)hi32(t) + a_hi);  // bits 32..95
@@ -55,9 +55,29 @@ __device__ __forceinline__ F61 p61_step_x32(F61 y, uint32_t x, uint64_t a_lo, ui
 }
 __device__ __forceinline__ F61 p61_step_x32(F61 y, uint32_t x, F61 a) { return p61_step_x32(y, x, a.w0, a.w1); }
 
+// A Horner step that folds at bit 64 instead of bit 61: for y < 2^64 and
+// x < 2^32, P = y*x + a < 2^96 + 2^61 has P >> 64 < 2^32, and 2^64 = 8 (mod p),
+// so P = (P mod 2^64) + 8 * (P >> 64) (mod p), one v_mad_u64_u32 (the move
+// that puts u's low word next to t's is the only other cost): four full-slot
+// instructions against the five of p61_step_x32.  The sum is exact unless it
+// carries out of 64 bits (then the result is 8 short modulo p); the
+// instruction's carry-out lane mask is or-ed into `carry`, which the caller
+// tests once per tile (a carry needs P mod 2^64 >= 2^64 - 2^35: about one
+// lane-step in 2^30) and then recomputes with the exact steps.  The result is
+// any 64-bit value.
+__device__ __forceinline__ F61 p61_step_x32_lazy(F61 y, uint32_t x, F61 a, uint64_t& carry) {
+  const uint64_t t = mad64(y.w0, x, a.w0);                      // < 2^64
+  const uint64_t u = mad64(y.w1, x, (uint64_t)hi32(t) + a.w1);  // < 2^64: bits 32..95
+  const uint64_t low = ((uint64_t)lo32(u) << 32) | lo32(t);     // P mod 2^64
+  uint64_t r, c;
+  asm("v_mad_u64_u32 %0, %1, %2, 8, %3" : "=&v"(r), "=s"(c) : "v"(hi32(u)), "v"(low));
+  carry |= c;
+  return F61{lo32(r), hi32(r)};
+}
+
 // The low word of h = v mod p, given r = the last Horner step's fold of
 // y*x + a_0 + 1 (that step run with a_lo = a_0's low limb + 1).  r is congruent
-// to h + 1 with 1 <= r < 2^61 + 2^34 < 2p + 1, so r is h + 1 or h + 1 + p and
+// to h + 1 with 1 <= r < 2^61 + 2^35 < 2p + 1, so r is h + 1 or h + 1 + p and
 // z = r >> 61 tells which; h = r - z*p - 1, whose low word is
 // lo32(r) + z - 1 (p = 2^32 - 1 modulo 2^32).  This replaces the final
 // reduction (Algorithm 4 for v < 2p) where only the low word is needed.

@@ -56,21 +56,51 @@ __device__ __forceinline__ RowCoeffs<K, NP> load_row_coeffs(const uint4* __restr
 // reduction: a value < 2p congruent to h(x).
 template <int K, int NP>
 __device__ __forceinline__ F61 horner61_x32(const RowCoeffs<K, NP>& c, int q, uint32_t x) {
+  // the steps before the last fold at bit 64 (p61_step_x32_lazy); on a carry
+  // in any lane the wave takes the exact steps (see code61_x32)
+  uint64_t carry = 0;
   F61 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
 #pragma unroll
-  for (int i = K - 2; i >= 0; --i) y = p61_step_x32(y, x, F61{c.w[q * K + i][0], c.w[q * K + i][1]});
-  return y;
+  for (int i = K - 2; i >= 1; --i) y = p61_step_x32_lazy(y, x, F61{c.w[q * K + i][0], c.w[q * K + i][1]}, carry);
+  if (__builtin_expect(carry != 0, 0)) {
+    asm volatile("");  // keeps this path a branch, not a select
+    y = F61{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
+#pragma unroll
+    for (int i = K - 2; i >= 1; --i) y = p61_step_x32(y, x, F61{c.w[q * K + i][0], c.w[q * K + i][1]});
+  }
+  return p61_step_x32(y, x, F61{c.w[q * K][0], c.w[q * K][1]});
 }
 
 // The code (low word of the reduced hash value) of key x < 2^32 under
 // polynomial q: Horner's rule (Algorithm 1) whose last step adds a_0 + 1, then
-// p61_lo_from_inc in place of the final reduction.
+// p61_lo_from_inc in place of the final reduction.  Every step folds at bit
+// 61 (p61_step_x32): exact, the path taken when a faster one saw a carry.
 template <int K, int NP>
-__device__ __forceinline__ uint32_t code61_x32(const RowCoeffs<K, NP>& c, int q, uint32_t x) {
+__device__ __forceinline__ uint32_t code61_x32_exact(const RowCoeffs<K, NP>& c, int q, uint32_t x) {
   F61 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
 #pragma unroll
   for (int i = K - 2; i >= 1; --i) y = p61_step_x32(y, x, F61{c.w[q * K + i][0], c.w[q * K + i][1]});
   y = p61_step_x32(y, x, (uint64_t)c.w[q * K][0] + 1u, c.w[q * K][1]);
+  return p61_lo_from_inc(y);
+}
+
+// The same value: the steps before the last fold at bit 64 (p61_step_x32_lazy,
+// one instruction less each); the last step folds at bit 61 so that
+// p61_lo_from_inc applies.  If any lane's lazy fold carried out of 64 bits the
+// wave recomputes with the exact steps (the carry mask is wave-uniform).
+template <int K, int NP>
+__device__ __forceinline__ uint32_t code61_x32(const RowCoeffs<K, NP>& c, int q, uint32_t x) {
+  uint64_t carry = 0;
+  F61 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
+#pragma unroll
+  for (int i = K - 2; i >= 1; --i) y = p61_step_x32_lazy(y, x, F61{c.w[q * K + i][0], c.w[q * K + i][1]}, carry);
+  y = p61_step_x32(y, x, (uint64_t)c.w[q * K][0] + 1u, c.w[q * K][1]);
+  if (__builtin_expect(carry != 0, 0)) {
+    // the volatile statement keeps the compiler from computing this path
+    // always and selecting its result
+    asm volatile("");
+    return code61_x32_exact<K, NP>(c, q, x);
+  }
   return p61_lo_from_inc(y);
 }
 
@@ -79,19 +109,26 @@ __device__ __forceinline__ uint32_t code61_x32(const RowCoeffs<K, NP>& c, int q,
 template <int K, int NP>
 __device__ __forceinline__ void code61_x32_pair(const RowCoeffs<K, NP>& c, int q, uint32_t xa, uint32_t xb,
                                                 uint32_t& ca, uint32_t& cb) {
+  uint64_t carry = 0;
   F61 ya{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
   F61 yb = ya;
 #pragma unroll
   for (int i = K - 2; i >= 1; --i) {
     const F61 a{c.w[q * K + i][0], c.w[q * K + i][1]};
-    ya = p61_step_x32(ya, xa, a);
-    yb = p61_step_x32(yb, xb, a);
+    ya = p61_step_x32_lazy(ya, xa, a, carry);
+    yb = p61_step_x32_lazy(yb, xb, a, carry);
   }
   const uint64_t a0 = (uint64_t)c.w[q * K][0] + 1u;
   ya = p61_step_x32(ya, xa, a0, c.w[q * K][1]);
   yb = p61_step_x32(yb, xb, a0, c.w[q * K][1]);
-  ca = p61_lo_from_inc(ya);
-  cb = p61_lo_from_inc(yb);
+  if (__builtin_expect(carry != 0, 0)) {
+    asm volatile("");  // as in code61_x32
+    ca = code61_x32_exact<K, NP>(c, q, xa);
+    cb = code61_x32_exact<K, NP>(c, q, xb);
+  } else {
+    ca = p61_lo_from_inc(ya);
+    cb = p61_lo_from_inc(yb);
+  }
 }
 
 template <int K, int NP>

@@ -439,3 +439,57 @@ def test_divmod_domain_flag():
         M.mersenne_status()
     assert e.value.status == M.CS_EDOMAIN
     M.mersenne_status()  # cleared
+
+
+def _lazy_fold_carries(y: int, x: int, a: int) -> bool:
+    """Whether folding P = y*x + a at bit 64 (P mod 2^64 + 8 (P >> 64)) carries out
+    of 64 bits: the case in which the library's faster Horner steps are inexact and
+    the wave recomputes its keys with the exact ones."""
+    p_ = y * x + a
+    return (p_ % (1 << 64)) + 8 * (p_ >> 64) >= 1 << 64
+
+
+@pytest.mark.parametrize("k", [4, 8])
+@pytest.mark.parametrize("mode", [0, 2])
+@pytest.mark.parametrize("path", ["auto", "rows", "lds", "global", "binned"])
+def test_lazy_fold_carry_path(path, mode, k):
+    """Keys and coefficients chosen so that the first Horner step's fold at bit 64
+    carries: a_{k-1} = 2^33 + 2, a_{k-2} = 0 and key 2^32 - 1 give P = 2^65 - 2.
+    Waves holding such a key must recompute with the exact steps; every counter
+    must equal the oracle's."""
+    top, x_bad = (1 << 33) + 2, (1 << 32) - 1
+    assert _lazy_fold_carries(top, x_bad, 0) and top < O.P61
+    rows, m = 3, 1 << 12
+    npoly = 2 if mode == 2 else 1
+    rng = np.random.default_rng(4242 + k)
+    coeffs = rng.integers(0, O.P61, size=(rows, npoly, k), dtype=np.uint64)
+    coeffs[0, :, k - 1] = top
+    coeffs[0, :, k - 2] = 0
+    coeffs[1, 0, k - 1] = top
+    n = 5 * 4096 + 77
+    keys = W.uniform_u32(31 + k, n).to(torch.int64)
+    keys[::97] = x_bad
+    keys[n - 1] = x_bad
+    w = W.bounded_int(31 + k, n, -100, 100)
+    keys, w = keys.to(DEV), w.to(DEV)
+    sk = M.Sketch(rows, m, prime=M.CS_P61, mode=mode, k=k, coeffs=coeffs.reshape(-1))
+    sk._coeffs = coeffs.reshape(-1)
+    if path != "auto":
+        sk.set_update_path({"rows": M.CS_PATH_ROWS, "lds": M.CS_PATH_LDS, "global": M.CS_PATH_GLOBAL,
+                            "binned": M.CS_PATH_BINNED}[path])
+    sk.update(keys, w)
+    _check_sketch(sk, keys, w)
+    # point queries hash the same keys (the first is 2^32 - 1)
+    qk = keys[:200].contiguous()
+    q = torch.empty(200, dtype=torch.int64, device=DEV)
+    sk.query(qk, q)
+    torch.cuda.synchronize()
+    table = sk.counters()
+    want_q = []
+    for x in _u64(qk):
+        vals = []
+        for r in range(rows):
+            b, s = O.bucket_sign(O.PRIME_P61, mode, m, sk._coeffs, r, int(x), k=k)
+            vals.append(s * int(table[r, b]))
+        want_q.append(sorted(vals)[rows // 2])
+    assert q.cpu().tolist() == want_q
