@@ -48,14 +48,15 @@ METRIC = "Gkeys/s into Count Sketch (p=2^61-1, 4-universal) + % of binding roofl
 # Algorithmic VALU lane-slots per key and row: the VALU instructions (register moves not
 # counted, so a lower bound) of the compiled straight-line hash + final reduction +
 # split of one row on gfx950, as the update kernels run it (the Horner steps before the
-# last fold at bit 64; the rare carry path left out), each weighted by its measured issue
-# cost (2, or 1 for the simple ones), plus 3 per row for the signed weight (v_xad_u32, 2)
-# and the counter address (v_and_b32, 1) (profiles/valu_ops_per_key_row.md):
-#   p61, key < 2^32, two-for-one: 13 64-bit + 4 other + 0 simple = 34, + 3 = 37
-#   p61 two polynomials: 26 64-bit + 5 other + 1 simple = 63, + 3 = 66
+# last fold at bit 64, the last step unfolded; the rare carry and guard paths left out),
+# each weighted by its measured issue cost (2, or 1 for the simple ones), plus 3 per row
+# for the signed weight (v_xad_u32, 2) and the counter address (v_and_b32, 1)
+# (profiles/valu_ops_per_key_row.md):
+#   p61, key < 2^32, two-for-one: 11 64-bit + 4 other + 1 simple = 31, + 3 = 34
+#   p61 two polynomials: 20 64-bit + 7 other + 3 simple = 57, + 3 = 60
 #   p61 any bucket count (Algorithm 8): 16 64-bit + 4 other + 1 simple = 41, + 3 = 44
 #   p89, 64-bit keys, two-for-one: 39 64-bit + 16 other + 2 simple = 112, + 3 = 115
-OPS_PER_KEY_ROW = {("p61", 0): 37, ("p61", 2): 66, ("p89", 0): 115, ("p61", 3): 44}
+OPS_PER_KEY_ROW = {("p61", 0): 34, ("p61", 2): 60, ("p89", 0): 115, ("p61", 3): 44}
 OPS_PER_KEY = 3  # the key's high-word test (domain check, one-limb path) and load addressing
 
 SKETCH_WORKLOADS = {
@@ -539,6 +540,11 @@ def run_served(args):
     total_keys = int(size.sum())
     _log(f"served: {n_tenants} tenants admitted, {n_req} requests ({total_keys} keys) in "
          f"{time.perf_counter() - t_gen:.1f} s")
+    # The arrival schedules at unit rate, made before any replay (scaled below by the
+    # measured rate): torch's CPU threads keep spinning for a while after an op, and in a
+    # replay that starts right after one they took the CPU quota from the server's worker
+    # thread (its first step then formed 5-8 ms late).
+    unit_arrivals = [W.poisson_arrivals(n_req, 1.0, seed=seed, stream=20 + i).numpy() for i in range(3)]
     srv.replay(reqs[: n_req // 20], np.zeros(n_req // 20))  # warm-up
     # the trace is marshalled once, outside the timed replays
     trace = srv.prepare(reqs)
@@ -557,7 +563,7 @@ def run_served(args):
 
     loads = []
     for i, frac in enumerate((0.3, 0.6, 0.9)):
-        arr = W.poisson_arrivals(n_req, frac * sat_rate, seed=seed, stream=20 + i).numpy()
+        arr = unit_arrivals[i] / (frac * sat_rate)
         r = srv.replay(trace, arr)
         bad += sum(1 for x in r if x.status != M.CS_OK)
         st = lat_stats(r)

@@ -83,6 +83,23 @@ __device__ __forceinline__ F61 p61_step_x32_lazy(F61 y, uint32_t x, F61 a, uint6
 // reduction (Algorithm 4 for v < 2p) where only the low word is needed.
 __device__ __forceinline__ uint32_t p61_lo_from_inc(F61 r) { return r.w0 + (r.w1 >> 29) - 1u; }
 
+// The last Horner step for y < 2^64 (what p61_step_x32_lazy returns) and
+// x < 2^32, giving the low word of h = P mod p for P = y*x + a (a < p) with
+// neither a fold nor a final reduction: P < 2^96, so P >> 61 < 2^35, and when
+// the bits 32..60 of P are below kP61LastGuard, P mod 2^61 < 2^61 - 2^35 and
+// the folded sum (P mod 2^61) + (P >> 61) is at most 2^61 - 2 < p, that is h
+// itself; its low word is lo32(P) + lo32(P >> 61) modulo 2^32 (one
+// v_alignbit_b32 and one add).  `bits` receives bits 32..60 of P: a lane
+// where they reach kP61LastGuard (about one in 2^26) is one the caller must
+// recompute with the exact steps.
+constexpr uint32_t kP61LastGuard = kMask29 - 7u;  // 0x1ffffff8: P mod 2^61 >= 2^61 - 2^35
+__device__ __forceinline__ uint32_t p61_last_lo(F61 y, uint32_t x, F61 a, uint32_t& bits) {
+  const uint64_t t = mad64(y.w0, x, a.w0);                      // < 2^64
+  const uint64_t u = mad64(y.w1, x, (uint64_t)hi32(t) + a.w1);  // P >> 32 < 2^64
+  bits = lo32(u) & kMask29;
+  return lo32(t) + funnel(hi32(u), lo32(u), 29);
+}
+
 // One Horner step for a key x < 2^60 (two-limb key).  Preconditions: y < 2p,
 // x < 2^60, a < p, so P = y*x + a < p^2 (Algorithm 1's invariant) and the
 // fold gives a value < 2p.

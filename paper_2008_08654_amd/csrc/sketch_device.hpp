@@ -84,50 +84,57 @@ __device__ __forceinline__ uint32_t code61_x32_exact(const RowCoeffs<K, NP>& c, 
   return p61_lo_from_inc(y);
 }
 
-// The same value: the steps before the last fold at bit 64 (p61_step_x32_lazy,
-// one instruction less each); the last step folds at bit 61 so that
-// p61_lo_from_inc applies.  If any lane's lazy fold carried out of 64 bits the
-// wave recomputes with the exact steps (the carry mask is wave-uniform).
+// The same value: the steps before the last at bit 64 (p61_step_x32_lazy, one
+// instruction less each), the last one without a fold (p61_last_lo).  If any
+// lane's lazy fold carried out of 64 bits, or any lane's last step is one
+// p61_last_lo does not cover, the wave recomputes with the exact steps (both
+// tests are wave-uniform).
 template <int K, int NP>
 __device__ __forceinline__ uint32_t code61_x32(const RowCoeffs<K, NP>& c, int q, uint32_t x) {
   uint64_t carry = 0;
   F61 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
 #pragma unroll
   for (int i = K - 2; i >= 1; --i) y = p61_step_x32_lazy(y, x, F61{c.w[q * K + i][0], c.w[q * K + i][1]}, carry);
-  y = p61_step_x32(y, x, (uint64_t)c.w[q * K][0] + 1u, c.w[q * K][1]);
-  if (__builtin_expect(carry != 0, 0)) {
+  uint32_t bits;
+  const uint32_t code = p61_last_lo(y, x, F61{c.w[q * K][0], c.w[q * K][1]}, bits);
+  if (__builtin_expect(carry != 0 || __any(bits >= kP61LastGuard), 0)) {
     // the volatile statement keeps the compiler from computing this path
     // always and selecting its result
     asm volatile("");
     return code61_x32_exact<K, NP>(c, q, x);
   }
-  return p61_lo_from_inc(y);
+  return code;
 }
 
-// The same for two keys, their steps interleaved: the two chains are
-// independent, so each fills the other's dependency stalls.
-template <int K, int NP>
-__device__ __forceinline__ void code61_x32_pair(const RowCoeffs<K, NP>& c, int q, uint32_t xa, uint32_t xb,
-                                                uint32_t& ca, uint32_t& cb) {
+// The same for NK keys (NK even), two keys' steps interleaved (the chains are
+// independent, so each fills the other's dependency stalls), with one test for
+// all of them: the largest of the last steps' bits 32..60 is compared once.
+template <int K, int NP, int NK>
+__device__ __forceinline__ void code61_x32_tile(const RowCoeffs<K, NP>& c, int q, const uint32_t (&x)[NK],
+                                                uint32_t (&code)[NK]) {
+  static_assert(NK % 2 == 0, "keys are hashed in pairs");
   uint64_t carry = 0;
-  F61 ya{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
-  F61 yb = ya;
+  uint32_t top = 0;
+  const F61 a0{c.w[q * K][0], c.w[q * K][1]};
 #pragma unroll
-  for (int i = K - 2; i >= 1; --i) {
-    const F61 a{c.w[q * K + i][0], c.w[q * K + i][1]};
-    ya = p61_step_x32_lazy(ya, xa, a, carry);
-    yb = p61_step_x32_lazy(yb, xb, a, carry);
+  for (int j = 0; j < NK; j += 2) {
+    F61 ya{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
+    F61 yb = ya;
+#pragma unroll
+    for (int i = K - 2; i >= 1; --i) {
+      const F61 a{c.w[q * K + i][0], c.w[q * K + i][1]};
+      ya = p61_step_x32_lazy(ya, x[j], a, carry);
+      yb = p61_step_x32_lazy(yb, x[j + 1], a, carry);
+    }
+    uint32_t ba, bb;
+    code[j] = p61_last_lo(ya, x[j], a0, ba);
+    code[j + 1] = p61_last_lo(yb, x[j + 1], a0, bb);
+    top = max(top, max(ba, bb));
   }
-  const uint64_t a0 = (uint64_t)c.w[q * K][0] + 1u;
-  ya = p61_step_x32(ya, xa, a0, c.w[q * K][1]);
-  yb = p61_step_x32(yb, xb, a0, c.w[q * K][1]);
-  if (__builtin_expect(carry != 0, 0)) {
+  if (__builtin_expect(carry != 0 || __any(top >= kP61LastGuard), 0)) {
     asm volatile("");  // as in code61_x32
-    ca = code61_x32_exact<K, NP>(c, q, xa);
-    cb = code61_x32_exact<K, NP>(c, q, xb);
-  } else {
-    ca = p61_lo_from_inc(ya);
-    cb = p61_lo_from_inc(yb);
+#pragma unroll
+    for (int j = 0; j < NK; ++j) code[j] = code61_x32_exact<K, NP>(c, q, x[j]);
   }
 }
 
@@ -536,10 +543,7 @@ __device__ __forceinline__ void row_update(const RowArgs<KeyT, WT>& args, const 
     int32_t sw[NK];
     if constexpr (PRIME == kPrime61 && MODE == kTwoForOne && !WIDE && NK % 2 == 0) {
       // the low-bit split: the code is the low word of the reduced hash
-#pragma unroll
-      for (int j = 0; j < NK; j += 2) {
-        code61_x32_pair<K, NP>(c, 0, x0[j], x0[j + 1], code[j], code[j + 1]);
-      }
+      code61_x32_tile<K, NP, NK>(c, 0, x0, code);
     } else {
 #pragma unroll
       for (int j = 0; j < NK; ++j) code[j] = bucket_code<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m);

@@ -8,6 +8,10 @@ against Python's exact integers:
   8 short (the kernels detect that case and take the fold at bit 61);
 * the fold at bit 61 of y*x + a_0 + 1 is r = h + 1 or h + 1 + p for
   h = (y*x + a_0) mod p, so the low word of h is lo32(r) + (r >> 61) - 1;
+* for y < 2^64 the last step needs no fold at all: P = y*x + a_0 < 2^96, and
+  unless bits 32..60 of P reach 2^29 - 8, (P mod 2^61) + (P >> 61) < p is h, so
+  the low word of h is lo32(P) + lo32(P >> 61) (the kernels send the wave to the
+  exact steps when a lane's bits reach that bound);
 * the same for p = 2^89 - 1 with r >> 89;
 * a 16-bit field's wrap test, taken in 32 bits, is exact for every 32-bit
   signed weight, and the carried multiples of 2^16 are floor((f + s*w) / 2^16).
@@ -87,6 +91,43 @@ def test_last_step_with_a0_plus_one_gives_the_low_word():
     y, x = 1, P61 - 1
     r = exact_step(y, x, 1, 0)
     assert ((r & M32) + (r >> 61) - 1) & M32 == (P61 - 1) & M32
+
+
+GUARD = (1 << 29) - 8
+
+
+def last_lo(y: int, x: int, a: int) -> tuple[int, int]:
+    """The kernel's unfolded last step on 32-bit limbs: (lo32(t) + lo32(u >> 29)) mod
+    2^32 and bits 32..60 of P, for t = y0 x + a0, u = y1 x + t_hi + a1 = P >> 32."""
+    y0, y1, a0, a1 = y & M32, y >> 32, a & M32, a >> 32
+    t = y0 * x + a0
+    assert t <= M64
+    u = y1 * x + (t >> 32) + a1
+    assert u <= M64
+    return ((t & M32) + ((u >> 29) & M32)) & M32, u & ((1 << 29) - 1)
+
+
+def test_unfolded_last_step_gives_the_low_word_below_the_guard():
+    rng = random.Random(96)
+    guarded = 0
+    cases = list(_values(rng, 20000))
+    # values of P just below, at and above the bound, and P = p, 2p (where the
+    # unfolded sum is not yet reduced)
+    for P in (P61, 2 * P61, P61 - 1, (GUARD << 32) - 1, GUARD << 32, (GUARD << 32) + M32, (1 << 61) + 5):
+        cases += [(1, x, P - x) for x in (0, 1, 12345) if 0 <= P - x < P61]
+    for i, (y, x, a) in enumerate(cases):
+        h = (y * x + a) % P61
+        lo, bits = last_lo(y, x, a)
+        assert bits == ((y * x + a) >> 32) & ((1 << 29) - 1)
+        if bits >= GUARD:
+            guarded += 135 <= i < 20135  # the random values, not the edge or constructed ones
+            continue
+        assert lo == h & M32
+    # the bound is needed: P = p (bits 32..60 all ones) has h = 0 but lo32(P) = 2^32 - 1
+    lo, bits = last_lo(1, 0, P61)
+    assert bits >= GUARD and lo != 0
+    # a random lane reaches the bound about once in 2^26
+    assert guarded <= 2
 
 
 def test_last_step_p89_low_word():

@@ -493,3 +493,37 @@ def test_lazy_fold_carry_path(path, mode, k):
             vals.append(s * int(table[r, b]))
         want_q.append(sorted(vals)[rows // 2])
     assert q.cpu().tolist() == want_q
+
+
+@pytest.mark.parametrize("k", [2, 4, 8])
+@pytest.mark.parametrize("mode", [0, 2])
+@pytest.mark.parametrize("path", ["auto", "rows", "lds", "global", "binned"])
+def test_last_step_guard_path(path, mode, k):
+    """Coefficients chosen so that the last Horner step of key 2^32 - 1 reaches
+    P = y*x + a_0 = p exactly (a_1 = 2^29, a_0 = 2^29 - 1, higher ones 0, so y = 2^29):
+    bits 32..60 of P are all ones and the unfolded low word lo32(P) + lo32(P >> 61)
+    would be 2^32 - 1 where h = 0.  Waves holding such a key must recompute with the
+    exact steps; every counter must equal the oracle's."""
+    x_bad = (1 << 32) - 1
+    assert (1 << 29) * x_bad + (1 << 29) - 1 == O.P61
+    rows, m = 3, 1 << 12
+    npoly = 2 if mode == 2 else 1
+    rng = np.random.default_rng(2929 + k)
+    coeffs = rng.integers(0, O.P61, size=(rows, npoly, k), dtype=np.uint64)
+    for r, a0 in ((0, (1 << 29) - 1), (1, (1 << 29) - 2)):
+        coeffs[r, :, 2:] = 0
+        coeffs[r, :, 1] = 1 << 29
+        coeffs[r, :, 0] = a0
+    n = 5 * 4096 + 77
+    keys = W.uniform_u32(53 + k, n).to(torch.int64)
+    keys[::97] = x_bad
+    keys[n - 1] = x_bad
+    w = W.bounded_int(53 + k, n, -100, 100)
+    keys, w = keys.to(DEV), w.to(DEV)
+    sk = M.Sketch(rows, m, prime=M.CS_P61, mode=mode, k=k, coeffs=coeffs.reshape(-1))
+    sk._coeffs = coeffs.reshape(-1)
+    if path != "auto":
+        sk.set_update_path({"rows": M.CS_PATH_ROWS, "lds": M.CS_PATH_LDS, "global": M.CS_PATH_GLOBAL,
+                            "binned": M.CS_PATH_BINNED}[path])
+    sk.update(keys, w)
+    _check_sketch(sk, keys, w)
