@@ -55,8 +55,8 @@ METRIC = "Gkeys/s into Count Sketch (p=2^61-1, 4-universal) + % of binding roofl
 #   p61, key < 2^32, two-for-one: 11 64-bit + 4 other + 1 simple = 31, + 3 = 34
 #   p61 two polynomials: 20 64-bit + 7 other + 3 simple = 57, + 3 = 60
 #   p61 any bucket count (Algorithm 8): 16 64-bit + 4 other + 1 simple = 41, + 3 = 44
-#   p89, 64-bit keys, two-for-one: 39 64-bit + 16 other + 2 simple = 112, + 3 = 115
-OPS_PER_KEY_ROW = {("p61", 0): 34, ("p61", 2): 60, ("p89", 0): 115, ("p61", 3): 44}
+#   p89, 64-bit keys, two-for-one: 35 64-bit + 13 other + 3 simple = 99, + 3 = 102
+OPS_PER_KEY_ROW = {("p61", 0): 34, ("p61", 2): 60, ("p89", 0): 102, ("p61", 3): 44}
 OPS_PER_KEY = 3  # the key's high-word test (domain check, one-limb path) and load addressing
 
 SKETCH_WORKLOADS = {

@@ -183,6 +183,28 @@ __device__ __forceinline__ F89 p89_step(F89 y, uint32_t x0, uint32_t x1, F89 a) 
 // as p61_lo_from_inc: 1 <= r < 2^89 + 2^65 < 2p + 1, z = r >> 89 in {0, 1}.
 __device__ __forceinline__ uint32_t p89_lo_from_inc(F89 r) { return r.w0 + (r.w2 >> 25) - 1u; }
 
+// The last Horner step without a fold, as p61_last_lo: for y < 2p and a < p,
+// P = y*x + a < 2^154 has P >> 89 < 2^65, so when bits 64..88 of P are below
+// kP89LastGuard, P mod 2^89 < 2^89 - 2^65 and (P mod 2^89) + (P >> 89) is at
+// most 2^89 - 2 < p, that is h itself, whose low word is lo32(P) + lo32(P >> 89).
+// `bits` receives bits 64..88 of P; a lane where they reach the bound (about
+// one in 2^24) is one the caller must finish with the fold (p89_step).
+constexpr uint32_t kP89LastGuard = kMask25 - 1u;  // 2^25 - 2: P mod 2^89 >= 2^89 - 2^65
+__device__ __forceinline__ uint32_t p89_last_lo(F89 y, uint32_t x0, uint32_t x1, F89 a, uint32_t& bits) {
+  uint64_t t = mad64(y.w0, x0, a.w0);
+  const uint32_t p0 = lo32(t);
+  t = mad64(y.w0, x1, (uint64_t)hi32(t) + a.w1);
+  uint64_t u = mad64(y.w1, x0, lo32(t));
+  uint64_t c = (uint64_t)hi32(t) + hi32(u);
+  t = mad64(y.w1, x1, c);
+  u = mad64(y.w2, x0, (uint64_t)lo32(t) + a.w2);
+  const uint32_t p2 = lo32(u);
+  c = (uint64_t)hi32(t) + hi32(u);
+  const uint32_t p3 = lo32(mad64(y.w2, x1, c));
+  bits = p2 & kMask25;
+  return p0 + funnel(p3, p2, 25);  // lo32(P) + lo32(P >> 89)
+}
+
 // y < 2p -> y mod p, branch-free (z = (y+1) >> 89 in {0,1}; (y+z) & p).
 __device__ __forceinline__ F89 p89_final(F89 y) {
   uint64_t s = (uint64_t)y.w0 + 1;

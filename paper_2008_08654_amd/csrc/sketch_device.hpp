@@ -166,15 +166,23 @@ __device__ __forceinline__ F89 hash89(const RowCoeffs<K, NP>& c, int q, uint32_t
 }
 
 // The low word of the reduced hash value of key (x0, x1) over 2^89 - 1, as
-// code61_x32.
+// code61_x32: the last Horner step unfolded (p89_last_lo); if any lane's last
+// step is one that does not cover, the wave takes that step with the fold
+// (adding a_0 + 1, then p89_lo_from_inc).
 template <int K, int NP>
 __device__ __forceinline__ uint32_t code89(const RowCoeffs<K, NP>& c, int q, uint32_t x0, uint32_t x1) {
   F89 y{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1], c.w[q * K + K - 1][2]};
 #pragma unroll
   for (int i = K - 2; i >= 1; --i)
     y = p89_step(y, x0, x1, F89{c.w[q * K + i][0], c.w[q * K + i][1], c.w[q * K + i][2]});
-  y = p89_step(y, x0, x1, F89{c.w[q * K][0], c.w[q * K][1], c.w[q * K][2]}, (uint64_t)c.w[q * K][0] + 1u);
-  return p89_lo_from_inc(y);
+  const F89 a0{c.w[q * K][0], c.w[q * K][1], c.w[q * K][2]};
+  uint32_t bits;
+  const uint32_t code = p89_last_lo(y, x0, x1, a0, bits);
+  if (__builtin_expect(__any(bits >= kP89LastGuard), 0)) {
+    asm volatile("");  // as in code61_x32
+    return p89_lo_from_inc(p89_step(y, x0, x1, a0, (uint64_t)a0.w0 + 1u));
+  }
+  return code;
 }
 
 // Bucket and sign bit of key (x0, x1) under a row's coefficients.  WIDE
@@ -654,18 +662,18 @@ __device__ __forceinline__ uint32_t rows_wave_tile_slow(const RowArgs<KeyT, WT>&
   return bad;
 }
 
-// One wave tile `wt` (64 * KPT keys, loaded into kk, ww when the tile is full)
-// of the rows of the block's group (first row r0; c1 holds row r0's
-// coefficients, used when the group is that one row).  Common case: a full
-// tile whose keys have one limb (p61) and whose weights fit the fields; the
-// rest goes to the general path.  Returns domain-error bits.
+// One wave tile `wt` (64 * KPT keys, loaded into kk, ww when the tile is full:
+// `full`, the same for all lanes) of the rows of the block's group (first row
+// r0; c1 holds row r0's coefficients, used when the group is that one row).
+// Common case: a full tile whose keys have one limb (p61) and whose weights fit
+// the fields; the rest goes to the general path.  Returns domain-error bits.
 template <int PRIME, int MODE, int K, int NP, int KPT, typename KeyT, typename WT>
 __device__ __forceinline__ uint32_t rows_wave_tile(const RowArgs<KeyT, WT>& args, const RowCoeffs<K, NP>& c1, bool one,
-                                                   uint32_t r0, uint32_t* words, uint64_t wt,
+                                                   uint32_t r0, uint32_t* words, uint64_t wt, bool full,
                                                    const KeyT (&kk)[KPT], const WT (&ww)[KPT], uint32_t lane) {
   constexpr uint64_t kWt = 64 * KPT;
   uint32_t bad = 0;
-  if ((wt + 1) * kWt <= args.n) {
+  if (full) {
     uint32_t x0[KPT], x1[KPT];
     int32_t wf[KPT];
     bool big = false;
@@ -762,9 +770,12 @@ __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> arg
   for (uint32_t i = threadIdx.x; i < nwords; i += kRowBlock) words[i] = 0x80008000u;
   __syncthreads();
   const uint32_t lane = threadIdx.x & 63;
-  const uint64_t W = (args.n + 64 * kRowKpt - 1) / (64 * kRowKpt);  // wave tiles
+  // wave tiles (at most 2^40 keys per launch: fewer than 2^31) and the full ones
+  // among them; 32-bit tile indices keep the loop's tests in scalar compares
+  const uint32_t W = (uint32_t)((args.n + 64 * kRowKpt - 1) / (64 * kRowKpt));
+  const uint32_t Wfull = (uint32_t)(args.n / (64 * kRowKpt));
   // the XCD ranges end where the pool begins: the pool blocks' share of the tiles
-  const uint64_t Wx = NR > X ? W * RB / per_xcd : W;
+  const uint32_t Wx = NR > X ? (uint32_t)((uint64_t)W * RB / per_xcd) : W;
   uint32_t bad = 0;
   // a group of one row keeps that row's coefficients for the whole launch
   const auto c1 = load_row_coeffs<K, NP>(args.coeffs + (size_t)r0 * NP * K);
@@ -772,7 +783,8 @@ __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> arg
   constexpr uint64_t kWt = 64 * kRowKpt;  // keys per wave tile
   for (uint32_t k = 0; k < NR; ++k) {
     const uint32_t x = home + k < NR ? home + k : home + k - NR;
-    const uint64_t lo = x < X ? Wx * x / X : Wx, hi = x < X ? Wx * (x + 1) / X : W;
+    const uint32_t lo = x < X ? (uint32_t)((uint64_t)Wx * x / X) : Wx;
+    const uint32_t hi = x < X ? (uint32_t)((uint64_t)Wx * (x + 1) / X) : W;
     uint32_t* const q = args.queues + x * G + g;
     if (k > 0) {
       // Another XCD's range: most are drained by the time a wave gets here.
@@ -782,7 +794,7 @@ __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> arg
       // with them cost more than the hashing of a small update).
       uint32_t seen = 0;
       if (lane == 0) seen = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (lo + (uint64_t)__builtin_amdgcn_readfirstlane(seen) * kRowChunk >= hi) continue;
+      if (__builtin_amdgcn_readfirstlane(seen) * kRowChunk >= hi - lo) continue;
     }
     // the next chunk is taken before the current one is processed, so the
     // atomic's round trip overlaps the hashing
@@ -790,17 +802,21 @@ __global__ __launch_bounds__(kRowBlock) void k_update_rows(RowArgs<KeyT, WT> arg
     if (lane == 0) next = atomic_add_ahead(q, 1u);
     for (;;) {
       const uint32_t c = __builtin_amdgcn_readfirstlane(next);
-      const uint64_t wt0 = lo + (uint64_t)c * kRowChunk;
-      if (wt0 >= hi) break;
+      // 32 bits hold c * kRowChunk: a counter passes the range's chunks by at
+      // most one per wave (each takes one chunk too many)
+      if (c * kRowChunk >= hi - lo) break;
+      const uint32_t wt0 = lo + c * kRowChunk;
       if (lane == 0) next = atomic_add_ahead(q, 1u);
-      const uint64_t wt1 = wt0 + kRowChunk < hi ? wt0 + kRowChunk : hi;
-      for (uint64_t wt = wt0; wt < wt1; ++wt) {
+      const uint32_t wt1 = hi - wt0 > kRowChunk ? wt0 + kRowChunk : hi;
+      for (uint32_t wt = wt0; wt < wt1; ++wt) {
         KeyT ka[kRowKpt];
         WT wa[kRowKpt];
-        if ((wt + 1) * kWt <= args.n)
-          tile_issue<kRowKpt>(args.keys + wt * kWt + lane, args.weights + wt * kWt + lane, ka, wa);
+        const bool full = wt < Wfull;
+        if (full)
+          tile_issue<kRowKpt>(args.keys + (uint64_t)wt * kWt + lane, args.weights + (uint64_t)wt * kWt + lane, ka,
+                              wa);
         __builtin_amdgcn_sched_barrier(0);
-        bad |= rows_wave_tile<PRIME, MODE, K, NP, kRowKpt>(args, c1, one, r0, words, wt, ka, wa, lane);
+        bad |= rows_wave_tile<PRIME, MODE, K, NP, kRowKpt>(args, c1, one, r0, words, wt, full, ka, wa, lane);
       }
     }
   }
@@ -887,9 +903,10 @@ __global__ __launch_bounds__(kRowBlock) void k_batch_rows(const BatchSketch* __r
       for (uint64_t wt = item.wt_begin + wave; wt < item.wt_end; wt += kRowBlock / 64) {
         KeyT ka[KPT];
         WT wa[KPT];
-        if ((wt + 1) * kWt <= a.n) tile_issue<KPT>(a.keys + wt * kWt + lane, a.weights + wt * kWt + lane, ka, wa);
+        const bool full = (wt + 1) * kWt <= a.n;
+        if (full) tile_issue<KPT>(a.keys + wt * kWt + lane, a.weights + wt * kWt + lane, ka, wa);
         __builtin_amdgcn_sched_barrier(0);
-        bad |= rows_wave_tile<PRIME, MODE, K, NP, KPT>(a, c1, one, item.r0, words, wt, ka, wa, lane);
+        bad |= rows_wave_tile<PRIME, MODE, K, NP, KPT>(a, c1, one, item.r0, words, wt, full, ka, wa, lane);
       }
       __syncthreads();
       rows_flush(a, item.r0, words, nwords, item.spread & 0xFFFFu, item.spread >> 16);

@@ -12,7 +12,8 @@ against Python's exact integers:
   unless bits 32..60 of P reach 2^29 - 8, (P mod 2^61) + (P >> 61) < p is h, so
   the low word of h is lo32(P) + lo32(P >> 61) (the kernels send the wave to the
   exact steps when a lane's bits reach that bound);
-* the same for p = 2^89 - 1 with r >> 89;
+* the same for p = 2^89 - 1 with r >> 89, and its unfolded last step (y < 2p,
+  bits 64..88 of P below 2^25 - 2);
 * a 16-bit field's wrap test, taken in 32 bits, is exact for every 32-bit
   signed weight, and the carried multiples of 2^16 are floor((f + s*w) / 2^16).
 """
@@ -139,6 +140,25 @@ def test_last_step_p89_low_word():
         r = (P & P89) + (P >> 89)
         assert r < 2 * P89 + 1
         assert ((r & M32) + (r >> 89) - 1) & M32 == h & M32
+
+
+def test_unfolded_last_step_p89():
+    rng = random.Random(8989)
+    guard = (1 << 25) - 2
+    hits = 0
+    cases = [(rng.randrange(2 * P89), rng.getrandbits(64), rng.randrange(P89)) for _ in range(20000)]
+    cases += [(1 << 25, M64, (1 << 25) - 1), (1 << 25, M64, (1 << 25) - 2), (2 * P89 - 1, M64, P89 - 1)]
+    for i, (y, x, a) in enumerate(cases):
+        P = y * x + a
+        assert P >> 89 < 1 << 65
+        if (P >> 64) & ((1 << 25) - 1) >= guard:
+            hits += i < 20000
+            continue
+        assert ((P & M32) + ((P >> 89) & M32)) & M32 == (P % P89) & M32
+    # the constructed case of the GPU test: P = p, h = 0, the unfolded word 2^32 - 1
+    P = (1 << 25) * M64 + (1 << 25) - 1
+    assert P == P89 and (P >> 64) & ((1 << 25) - 1) >= guard and (P & M32) + ((P >> 89) & M32) == M32
+    assert hits <= 2
 
 
 def test_field_wrap_test_is_exact_for_32_bit_weights():

@@ -527,3 +527,38 @@ def test_last_step_guard_path(path, mode, k):
                             "binned": M.CS_PATH_BINNED}[path])
     sk.update(keys, w)
     _check_sketch(sk, keys, w)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+@pytest.mark.parametrize("path", ["auto", "rows", "lds", "global", "binned"])
+def test_last_step_guard_path_p89(path, mode):
+    """p = 2^89 - 1, k = 4: a_3 = a_2 = 0, a_1 = 2^25 and a_0 = 2^25 - 1 give key
+    2^64 - 1 the last step P = p: bits 64..88 of P are all ones and the unfolded low
+    word would be 2^32 - 1 where h = 0.  Waves holding such a key must take that step
+    with the fold; every counter must equal the oracle's."""
+    x_bad = (1 << 64) - 1
+    assert (1 << 25) * x_bad + (1 << 25) - 1 == O.P89
+    rows, m, k = 3, 1 << 12, 4
+    npoly = 2 if mode == 2 else 1
+    rng = np.random.default_rng(8989)
+    vals = [[[int(rng.integers(0, 1 << 62)) * (1 << 27) % O.P89 for _ in range(k)] for _ in range(npoly)]
+            for _ in range(rows)]
+    for r, a0 in ((0, (1 << 25) - 1), (1, (1 << 25) - 2)):
+        for q in range(npoly):
+            vals[r][q] = [a0, 1 << 25, 0, 0]
+    coeffs = np.array([[v & ((1 << 64) - 1), v >> 64] for row in vals for poly in row for v in poly],
+                      dtype=np.uint64)
+    n = 5 * 4096 + 77
+    keys = W.uniform_u64(71, n)
+    keys[::97] = -1  # 2^64 - 1
+    keys[n - 1] = -1
+    w = W.bounded_int(71, n, -100, 100)
+    keys, w = keys.to(DEV), w.to(DEV)
+    sk = M.Sketch(rows, m, prime=M.CS_P89, mode=mode, k=k, coeffs=coeffs.reshape(-1))
+    sk._coeffs = coeffs
+    assert np.array_equal(sk.coeffs(), coeffs)
+    if path != "auto":
+        sk.set_update_path({"rows": M.CS_PATH_ROWS, "lds": M.CS_PATH_LDS, "global": M.CS_PATH_GLOBAL,
+                            "binned": M.CS_PATH_BINNED}[path])
+    sk.update(keys, w)
+    _check_sketch(sk, keys, w)
