@@ -16,6 +16,8 @@
 // two-pass workspace, which stream order makes safe.
 #include <hip/hip_runtime.h>
 
+#include <sys/prctl.h>
+
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -589,16 +591,17 @@ extern "C" cs_status cs_server_replay(cs_server* S, const cs_server_request* req
   }
   std::vector<uint64_t> tickets(count, 0);
   std::vector<cs_status> sub(count, CS_OK);
+  const int slack = prctl(PR_GET_TIMERSLACK, 0, 0, 0, 0);
+  (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0, 0, 0);  // this thread's sleeps end within ~1 us
   // every request that is due goes into the queue under one lock acquisition
   const uint64_t t0 = now_ns();
   for (uint32_t i = 0; i < count;) {
     const uint64_t target = t0 + (uint64_t)(arrival_s[i] * 1e9);
-    for (uint64_t t = now_ns(); t < target; t = now_ns()) {
-      if (target - t > 300000)
-        std::this_thread::sleep_for(std::chrono::nanoseconds(target - t - 200000));
-      else
-        std::this_thread::yield();
-    }
+    // Sleep until the arrival rather than spin: a thread that spins with yields
+    // kept the CPU the worker woke on for milliseconds.  The timer slack is
+    // cut to 1 us for the replay (see below), so a wake-up is a few us late.
+    for (uint64_t t = now_ns(); t < target; t = now_ns())
+      std::this_thread::sleep_for(std::chrono::nanoseconds(target - t));
     const uint64_t now = now_ns();
     {
       std::lock_guard<std::mutex> lk(S->mu);
@@ -611,6 +614,7 @@ extern "C" cs_status cs_server_replay(cs_server* S, const cs_server_request* req
     }
     S->cv_work.notify_one();
   }
+  if (slack > 0) (void)prctl(PR_SET_TIMERSLACK, (unsigned long)slack, 0, 0, 0);
   cs_status first = CS_OK;
   for (uint32_t i = 0; i < count; ++i) {
     if (sub[i] != CS_OK) {
