@@ -57,20 +57,30 @@ __device__ __forceinline__ F61 p61_step_x32(F61 y, uint32_t x, F61 a) { return p
 
 // A Horner step that folds at bit 64 instead of bit 61: for y < 2^64 and
 // x < 2^32, P = y*x + a < 2^96 + 2^61 has P >> 64 < 2^32, and 2^64 = 8 (mod p),
-// so P = (P mod 2^64) + 8 * (P >> 64) (mod p), one v_mad_u64_u32 (the move
-// that puts u's low word next to t's is the only other cost): four full-slot
-// instructions against the five of p61_step_x32.  The sum is exact unless it
-// carries out of 64 bits (then the result is 8 short modulo p); the
-// instruction's carry-out lane mask is or-ed into `carry`, which the caller
-// tests once per tile (a carry needs P mod 2^64 >= 2^64 - 2^35: about one
-// lane-step in 2^30) and then recomputes with the exact steps.  The result is
-// any 64-bit value.
+// so P = (P mod 2^64) + 8 * (P >> 64) (mod p), one v_mad_u64_u32.  The two
+// partial products A = y0*x + a0 and B = y1*x + a1 are independent; P mod 2^64
+// is A with lo32(B) added to its high word (v_add_co_u32, in place, so the
+// pair needs no move) and P >> 64 is hi32(B) plus that carry
+// (v_addc_co_u32): five instructions and no register move, where adding
+// hi32(A) into B first costs four and two moves to pair the words.  The sum is
+// exact unless it carries out of 64 bits (then the result is 8 short modulo
+// p); the instruction's carry-out lane mask is or-ed into `carry`, which the
+// caller tests once per tile (a carry needs P mod 2^64 >= 2^64 - 2^35: about
+// one lane-step in 2^30) and then recomputes with the exact steps.  The result
+// is any 64-bit value.
 __device__ __forceinline__ F61 p61_step_x32_lazy(F61 y, uint32_t x, F61 a, uint64_t& carry) {
-  const uint64_t t = mad64(y.w0, x, a.w0);                      // < 2^64
-  const uint64_t u = mad64(y.w1, x, (uint64_t)hi32(t) + a.w1);  // < 2^64: bits 32..95
-  const uint64_t low = ((uint64_t)lo32(u) << 32) | lo32(t);     // P mod 2^64
+  const uint64_t A = mad64(y.w0, x, a.w0);  // y0 x + a0 < 2^64
+  const uint64_t B = mad64(y.w1, x, a.w1);  // y1 x + a1 < 2^64 - 2^32
+  // P = A + 2^32 B: P mod 2^64 = A + 2^32 lo32(B) (mod 2^64), whose carry goes
+  // into P >> 64 = hi32(B) + carry (< 2^32)
+  uint32_t mid = hi32(A), top;
+  asm("v_add_co_u32 %0, vcc, %0, %2\n\tv_addc_co_u32 %1, vcc, 0, %3, vcc"
+      : "+v"(mid), "=v"(top)
+      : "v"(lo32(B)), "v"(hi32(B))
+      : "vcc");
+  const uint64_t low = ((uint64_t)mid << 32) | lo32(A);  // P mod 2^64
   uint64_t r, c;
-  asm("v_mad_u64_u32 %0, %1, %2, 8, %3" : "=&v"(r), "=s"(c) : "v"(hi32(u)), "v"(low));
+  asm("v_mad_u64_u32 %0, %1, %2, 8, %3" : "=&v"(r), "=s"(c) : "v"(top), "v"(low));
   carry |= c;
   return F61{lo32(r), hi32(r)};
 }

@@ -109,10 +109,10 @@ __device__ __forceinline__ uint32_t code61_x32(const RowCoeffs<K, NP>& c, int q,
 // The same for NK keys (NK even), two keys' steps interleaved (the chains are
 // independent, so each fills the other's dependency stalls), with one test for
 // all of them: the largest of the last steps' bits 32..60 is compared once.
-template <int K, int NP, int NK>
-__device__ __forceinline__ void code61_x32_tile(const RowCoeffs<K, NP>& c, int q, const uint32_t (&x)[NK],
+template <int K, int NP, int NK, int NX>
+__device__ __forceinline__ void code61_x32_tile(const RowCoeffs<K, NP>& c, int q, const uint32_t (&x)[NX],
                                                 uint32_t (&code)[NK]) {
-  static_assert(NK % 2 == 0, "keys are hashed in pairs");
+  static_assert(NK % 2 == 0 && NK <= NX, "keys are hashed in pairs, the first NK of x");
   uint64_t carry = 0;
   uint32_t top = 0;
   const F61 a0{c.w[q * K][0], c.w[q * K][1]};
@@ -431,6 +431,16 @@ __device__ __forceinline__ void lds_block_update(const UpdateArgs<KeyT, WT>& arg
         for (int j = 0; j < kKpt; ++j) {
           uint32_t bk, m;
           bucket_mask<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m, bk, m);
+          if (ok[j]) atomicAdd(&row[bk], masked_signed(m, wv[j], wneg[j]));
+        }
+      } else if constexpr (PRIME == kPrime61 && MODE == kTwoForOne && kKpt % 2 == 0) {
+        // the low-bit split: the codes of the lane's keys with one guard test
+        uint32_t code[kKpt];
+        code61_x32_tile<K, NP, kKpt>(c, 0, x0, code);
+#pragma unroll
+        for (int j = 0; j < kKpt; ++j) {
+          const uint32_t bk = __builtin_amdgcn_ubfe(code[j], 1u, args.log2m);
+          const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)code[j], 0, 1);
           if (ok[j]) atomicAdd(&row[bk], masked_signed(m, wv[j], wneg[j]));
         }
       } else {
@@ -1215,8 +1225,12 @@ __device__ __forceinline__ void bin_rows_wave(const BA& args, uint32_t tile, uin
     const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
     uint32_t* const hrow = hist + r * NC;
     uint32_t code[kUse], gq[kUse], tick[kUse];
+    if constexpr (PRIME == kPrime61 && MODE == kTwoForOne && !WIDE && kUse % 2 == 0) {
+      code61_x32_tile<K, NP, kUse>(c, 0, x0, code);  // one guard test for the lane's keys
+    } else {
 #pragma unroll
-    for (int j = 0; j < kUse; ++j) code[j] = bucket_code<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m);
+      for (int j = 0; j < kUse; ++j) code[j] = bucket_code<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m);
+    }
 #pragma unroll
     for (int j = 0; j < kUse; ++j) {
       gq[j] = bitsel(rmask[j], __builtin_amdgcn_ubfe(code[j], log2r, args.log2g + 1u), spare);

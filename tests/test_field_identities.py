@@ -29,15 +29,20 @@ def fold61(v: int) -> int:
 
 
 def lazy_step(y: int, x: int, a: int) -> tuple[int, bool]:
-    """The kernel's bit-64 step on 32-bit limbs: t = y0 x + a0, u = y1 x + t_hi + a1,
-    then (u_lo:t_lo) + 8 u_hi in 64 bits, with its carry-out."""
+    """The kernel's bit-64 step on 32-bit limbs: A = y0 x + a0 and B = y1 x + a1, the
+    high word of A plus the low word of B with its carry into B's high word (the
+    v_add_co_u32 / v_addc_co_u32 pair), then (mid:A_lo) + 8 top in 64 bits, with its
+    carry-out."""
     y0, y1, a0, a1 = y & M32, y >> 32, a & M32, a >> 32
-    t = y0 * x + a0
-    assert t <= M64
-    u = y1 * x + (t >> 32) + a1
-    assert u <= M64
-    low = ((u & M32) << 32) | (t & M32)
-    s = low + 8 * (u >> 32)
+    A = y0 * x + a0
+    B = y1 * x + a1
+    assert A <= M64 and B <= M64
+    mid = (A >> 32) + (B & M32)
+    top = (B >> 32) + (mid >> 32)
+    assert top <= M32  # B < 2^64 - 2^32, so its high word takes the carry
+    low = ((mid & M32) << 32) | (A & M32)
+    assert low + (top << 64) == y * x + a  # the pair is P mod 2^64 and P >> 64
+    s = low + 8 * top
     return s & M64, s > M64
 
 
