@@ -116,9 +116,16 @@ __device__ __forceinline__ void code61_x32_tile(const RowCoeffs<K, NP>& c, int q
   uint64_t carry = 0;
   uint32_t top = 0;
   const F61 a0{c.w[q * K][0], c.w[q * K][1]};
+  // the leading coefficient in vector registers: the first step's products
+  // then take their coefficient addends from scalar registers, as the later
+  // steps do, and need no copies of them
+  F61 top_c;
+  asm volatile("v_mov_b32 %0, %2\n\tv_mov_b32 %1, %3"
+               : "=v"(top_c.w0), "=v"(top_c.w1)
+               : "s"(c.w[q * K + K - 1][0]), "s"(c.w[q * K + K - 1][1]));
 #pragma unroll
   for (int j = 0; j < NK; j += 2) {
-    F61 ya{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1]};
+    F61 ya = top_c;
     F61 yb = ya;
 #pragma unroll
     for (int i = K - 2; i >= 1; --i) {
