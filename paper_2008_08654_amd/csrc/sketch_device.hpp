@@ -569,6 +569,14 @@ __device__ __forceinline__ void row_update(const RowArgs<KeyT, WT>& args, const 
     if constexpr (PRIME == kPrime61 && MODE == kTwoForOne && !WIDE && NK % 2 == 0) {
       // the low-bit split: the code is the low word of the reduced hash
       code61_x32_tile<K, NP, NK>(c, 0, x0, code);
+    } else if constexpr (PRIME == kPrime61 && MODE == kTwoPoly && !WIDE && NK % 2 == 0) {
+      // two polynomials: bucket from the first's low word, sign from the
+      // second's bit 0 (bucket_code's layout), each with one guard test
+      uint32_t sg[NK];
+      code61_x32_tile<K, NP, NK>(c, 0, x0, code);
+      code61_x32_tile<K, NP, NK>(c, 1, x0, sg);
+#pragma unroll
+      for (int j = 0; j < NK; ++j) code[j] = (code[j] << 1) | (sg[j] & 1u);
     } else {
 #pragma unroll
       for (int j = 0; j < NK; ++j) code[j] = bucket_code<PRIME, MODE, K, WIDE, NP>(c, x0[j], x1[j], args.log2m);
