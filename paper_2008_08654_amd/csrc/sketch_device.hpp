@@ -192,6 +192,31 @@ __device__ __forceinline__ uint32_t code89(const RowCoeffs<K, NP>& c, int q, uin
   return code;
 }
 
+// code89 for NK keys with one guard test: the steps before the last are kept
+// per key, so a wave with a lane at the guard only redoes the last step.
+template <int K, int NP, int NK>
+__device__ __forceinline__ void code89_tile(const RowCoeffs<K, NP>& c, int q, const uint32_t (&x0)[NK],
+                                            const uint32_t (&x1)[NK], uint32_t (&code)[NK]) {
+  const F89 a0{c.w[q * K][0], c.w[q * K][1], c.w[q * K][2]};
+  F89 y[NK];
+  uint32_t top = 0;
+#pragma unroll
+  for (int j = 0; j < NK; ++j) {
+    y[j] = F89{c.w[q * K + K - 1][0], c.w[q * K + K - 1][1], c.w[q * K + K - 1][2]};
+#pragma unroll
+    for (int i = K - 2; i >= 1; --i)
+      y[j] = p89_step(y[j], x0[j], x1[j], F89{c.w[q * K + i][0], c.w[q * K + i][1], c.w[q * K + i][2]});
+    uint32_t bits;
+    code[j] = p89_last_lo(y[j], x0[j], x1[j], a0, bits);
+    top = max(top, bits);
+  }
+  if (__builtin_expect(__any(top >= kP89LastGuard), 0)) {
+    asm volatile("");  // as in code61_x32
+#pragma unroll
+    for (int j = 0; j < NK; ++j) code[j] = p89_lo_from_inc(p89_step(y[j], x0[j], x1[j], a0, (uint64_t)a0.w0 + 1u));
+  }
+}
+
 // Bucket and sign bit of key (x0, x1) under a row's coefficients.  WIDE
 // selects the two-limb key path for p61.
 template <int PRIME, int MODE, int K, bool WIDE, int NP>
@@ -1159,10 +1184,32 @@ __global__ __launch_bounds__(kBlock) void k_bin(BinArgs<KeyT, WT> args) {
     for (uint32_t r = 0; r < args.rows; ++r) {
       const auto c = load_row_coeffs<K, NP>(args.coeffs + (size_t)r * NP * K);
       uint32_t rec[kKpt], grp[kKpt], tick[kKpt];
+      uint32_t codes[kKpt];
+      if constexpr (PRIME == kPrime89 && MODE == kTwoForOne) {
+        // a guard test per four keys (all of a lane's keys at once would hold
+        // too many registers)
+        constexpr int Q = kKpt % 2 == 0 ? 2 : kKpt;
+#pragma unroll
+        for (int j0 = 0; j0 < kKpt; j0 += Q) {
+          uint32_t qa[Q], qb[Q], qc[Q];
+#pragma unroll
+          for (int u = 0; u < Q; ++u) {
+            qa[u] = x0[j0 + u];
+            qb[u] = x1[j0 + u];
+          }
+          code89_tile<K, NP, Q>(c, 0, qa, qb, qc);
+#pragma unroll
+          for (int u = 0; u < Q; ++u) codes[j0 + u] = qc[u];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < kKpt; ++j)
+          codes[j] = wide ? bucket_code<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m)
+                          : bucket_code<PRIME, MODE, K, false, NP>(c, x0[j], x1[j], args.log2m);
+      }
 #pragma unroll
       for (int j = 0; j < kKpt; ++j) {
-        const uint32_t code = wide ? bucket_code<PRIME, MODE, K, true, NP>(c, x0[j], x1[j], args.log2m)
-                                   : bucket_code<PRIME, MODE, K, false, NP>(c, x0[j], x1[j], args.log2m);
+        const uint32_t code = codes[j];
         grp[j] = __builtin_amdgcn_ubfe(code, 1u + log2r, args.log2g);
         const int64_t sw = (code & 1u) ? -wv[j] : wv[j];
         rec[j] = (code << wb) | ((uint32_t)sw & wbmask);

@@ -530,15 +530,16 @@ def test_last_step_guard_path(path, mode, k):
 
 
 @pytest.mark.parametrize("mode", [0, 2])
-@pytest.mark.parametrize("path", ["auto", "rows", "lds", "global", "binned"])
-def test_last_step_guard_path_p89(path, mode):
+@pytest.mark.parametrize("path,log2m", [("auto", 12), ("rows", 12), ("lds", 12), ("global", 12), ("binned", 12),
+                                        ("binned", 18)])
+def test_last_step_guard_path_p89(path, log2m, mode):
     """p = 2^89 - 1, k = 4: a_3 = a_2 = 0, a_1 = 2^25 and a_0 = 2^25 - 1 give key
     2^64 - 1 the last step P = p: bits 64..88 of P are all ones and the unfolded low
     word would be 2^32 - 1 where h = 0.  Waves holding such a key must take that step
     with the fold; every counter must equal the oracle's."""
     x_bad = (1 << 64) - 1
     assert (1 << 25) * x_bad + (1 << 25) - 1 == O.P89
-    rows, m, k = 3, 1 << 12, 4
+    rows, m, k = 3, 1 << log2m, 4  # 2^18 buckets: more than 16 ranges, block tiles
     npoly = 2 if mode == 2 else 1
     rng = np.random.default_rng(8989)
     vals = [[[int(rng.integers(0, 1 << 62)) * (1 << 27) % O.P89 for _ in range(k)] for _ in range(npoly)]
